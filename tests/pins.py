@@ -1,0 +1,314 @@
+"""Checks that tie the oracle to facts outside itself.
+
+Each check raises AssertionError when the oracle disagrees with the paper,
+a closed form, a library routine or brute force.  ``test_oracle_pins`` runs
+them on the oracle as written; ``test_oracle_mutations`` plants plausible
+mistakes in the oracle (on the CPU) and requires at least one check to fail.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+import workloads as W
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def random_csr(n, density, seed, diag_shift=0.0):
+    r = rng(seed)
+    D = r.standard_normal((n, n)) * (r.random((n, n)) < density)
+    D += diag_shift * np.eye(n)
+    rows, cols = np.nonzero(D)
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr).astype(np.int32)
+    return W.CSR(n, row_ptr, cols.astype(np.int32), D[rows, cols]), D
+
+
+def dense_csr(D):
+    rows, cols = np.nonzero(D)
+    n = D.shape[0]
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(row_ptr, rows + 1, 1)
+    return W.CSR(n, np.cumsum(row_ptr).astype(np.int32), cols.astype(np.int32), D[rows, cols])
+
+
+# --- O1 SpMV -----------------------------------------------------------------
+def check_spmv_matches_dense():
+    A, D = random_csr(60, 0.15, 1)
+    x = rng(2).standard_normal(60)
+    y = O.spmv(A, x)
+    assert np.allclose(y, D @ x, rtol=0, atol=1e-13 * (np.abs(D) @ np.abs(x)).max()), "spmv != dense"
+    # an empty row and a full row
+    D2 = D.copy()
+    D2[5, :] = 0.0
+    D2[7, :] = rng(3).standard_normal(60)
+    A2 = dense_csr(D2)
+    assert np.allclose(O.spmv(A2, x), D2 @ x, rtol=1e-13, atol=1e-12)
+
+
+def check_spmv_integer_exact():
+    # b = A * ones of the 2D Laplacian is 4 - #neighbours: 2 corners, 1 edges, 0 inside
+    N = 64
+    A = W.laplace2d(N)
+    b = O.spmv(A, np.ones(A.n))
+    i = np.arange(A.n) % N
+    j = np.arange(A.n) // N
+    nb = (i > 0).astype(int) + (i < N - 1) + (j > 0) + (j < N - 1)
+    assert np.array_equal(b, 4.0 - nb), "integer SpMV not exact"
+    assert np.isclose(np.linalg.norm(b) ** 2, 264.0, rtol=0, atol=1e-12)
+
+
+def check_spmv_f32_bound():
+    # componentwise bound |y^ - y| <= gamma_w |A||x| (inner-product bound)
+    A = W.laplace3d(10)
+    x = rng(4).uniform(-1, 1, A.n).astype(np.float32)
+    y32 = O.spmv(A, x, np.float32).astype(np.float64)
+    y64 = O.spmv(A, x.astype(np.float64), np.float64)
+    absA = W.CSR(A.n, A.row_ptr, A.col_idx, np.abs(A.val.astype(np.float32)).astype(np.float64))
+    u = 2.0 ** -24
+    w = 7
+    gam = (w + 1) * u / (1 - (w + 1) * u)   # +1: the float32 rounding of A's values
+    bound = gam * O.spmv(absA, np.abs(x).astype(np.float64), np.float64)
+    assert np.all(np.abs(y32 - y64) <= bound + 1e-30), "float32 SpMV outside its bound"
+
+
+# --- O2 CGS2 / Arnoldi -----------------------------------------------------
+def _nonsym(n, seed):
+    r = rng(seed)
+    D = np.eye(n) * 4 + r.standard_normal((n, n)) / np.sqrt(n)
+    return dense_csr(D), D
+
+
+def check_arnoldi_orthogonal_and_hessenberg():
+    A, D = _nonsym(40, 5)
+    v0 = rng(6).standard_normal(40)
+    V, H, k = O.arnoldi(A, v0, 12)
+    assert k == 12
+    orth = np.linalg.norm(V.T @ V - np.eye(13))
+    assert orth < 1e-12, f"||V^T V - I|| = {orth}"
+    rel = np.linalg.norm(D @ V[:, :12] - V @ H) / (np.linalg.norm(D) * np.linalg.norm(V[:, :12]))
+    assert rel < 1e-14, f"Hessenberg relation {rel}"
+    assert np.all(np.diag(H, -1) > 0)
+
+
+def check_arnoldi_equals_qr_of_krylov():
+    A, D = _nonsym(12, 7)
+    v0 = rng(8).standard_normal(12)
+    k = 5
+    V, H, _ = O.arnoldi(A, v0, k)
+    K = np.empty((12, k + 1))
+    K[:, 0] = v0
+    for c in range(1, k + 1):
+        K[:, c] = D @ K[:, c - 1]
+    Q, R = np.linalg.qr(K)
+    Q = Q * np.sign(np.diag(R))
+    assert np.allclose(V, Q, atol=1e-10), "Arnoldi basis != QR of the Krylov matrix"
+
+
+# --- O3 Givens least squares --------------------------------------------------
+def check_givens_matches_lstsq():
+    r = rng(9)
+    m = 15
+    Hbar = np.triu(r.standard_normal((m + 1, m)), -1)
+    Hbar[np.arange(1, m + 1), np.arange(m)] = np.abs(Hbar[np.arange(1, m + 1), np.arange(m)]) + 0.1
+    gamma = 2.5
+    Hr = Hbar.copy()
+    cs, sn, g = np.zeros(m), np.zeros(m), np.zeros(m + 1)
+    g[0] = gamma
+    for j in range(m):
+        res = O.apply_givens_column(Hr[:, j], cs, sn, g, j)
+        yj = O.back_substitute(Hr[: j + 1, : j + 1], g[: j + 1])
+        rhs = np.zeros(j + 2)
+        rhs[0] = gamma
+        yl, *_ = np.linalg.lstsq(Hbar[: j + 2, : j + 1], rhs, rcond=None)
+        assert np.allclose(yj, yl, rtol=1e-10, atol=1e-12), "Givens y != lstsq"
+        true_res = np.linalg.norm(rhs - Hbar[: j + 2, : j + 1] @ yl)
+        assert np.isclose(res, true_res, rtol=1e-10, atol=1e-14), "implicit residual wrong"
+
+
+def check_back_substitute():
+    r = rng(10)
+    R = np.triu(r.standard_normal((9, 9))) + 3 * np.eye(9)
+    g = r.standard_normal(9)
+    assert np.allclose(O.back_substitute(R, g), np.linalg.solve(R, g), rtol=1e-12)
+
+
+# --- O4 GMRES ---------------------------------------------------------------
+def check_gmres_tiny_dense_solve():
+    A, D = _nonsym(30, 11)
+    b = rng(12).standard_normal(30)
+    out = O.gmres(A, b, np.zeros(30), 10, 1e-10, 500)
+    assert out.converged
+    x = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(out.x - x) / np.linalg.norm(x) <= 10 * kappa * 1e-10
+
+
+def check_gmres_brute_force_minimisation():
+    A, D = _nonsym(24, 13)
+    b = rng(14).standard_normal(24)
+    out = O.gmres(A, b, np.zeros(24), 24, 1e-14, 8, max_cycles=1)
+    K = np.empty((24, 8))
+    K[:, 0] = b
+    for c in range(1, 8):
+        K[:, c] = D @ K[:, c - 1]
+    bn = np.linalg.norm(b)
+    for j in range(1, 9):
+        AK = D @ K[:, :j]
+        c, *_ = np.linalg.lstsq(AK, b, rcond=None)
+        best = np.linalg.norm(b - AK @ c) / bn
+        assert np.isclose(out.implicit_history[j - 1], best, rtol=1e-7, atol=1e-15), \
+            f"step {j}: GMRES residual {out.implicit_history[j-1]} != Krylov minimum {best}"
+
+
+def check_gmres_finite_termination():
+    # A diagonal with 6 distinct eigenvalues: GMRES is exact after 6 steps
+    d = np.repeat([1.0, 2.0, 3.5, 5.0, 7.0, 11.0], 5)
+    D = np.diag(d)
+    A = dense_csr(D)
+    b = rng(15).uniform(0.5, 1.5, 30)
+    out = O.gmres(A, b, np.zeros(30), 20, 1e-12, 100)
+    assert out.converged and out.iters == 6, (out.iters, out.rel_res)
+
+
+def check_gmres_config1_counts():
+    p = W.config1_laplace2d()
+    out = O.gmres(p.A, p.b, np.zeros(p.A.n), 50, 1e-10, 5000)
+    assert out.converged and out.rel_res <= 1e-10
+    assert out.iters % 50 != 0  # mid-cycle stop of the float64 solver
+    err = np.linalg.norm(out.x - 1.0) / np.sqrt(p.A.n)
+    assert err <= 2e3 * 1e-10 * 10
+    return out
+
+
+# --- O5 GMRES-IR --------------------------------------------------------------
+def check_gmres_ir_config1():
+    p = W.config1_laplace2d()
+    d64 = O.gmres(p.A, p.b, np.zeros(p.A.n), 50, 1e-10, 5000)
+    ir = O.gmres_ir(p.A, p.b, np.zeros(p.A.n), 50, 1e-10, 5000)
+    assert ir.converged and ir.rel_res <= 1e-10
+    assert ir.iters % 50 == 0
+    assert ir.iters <= d64.iters + 3 * 50
+    # residual curves track: at each restart IR is within 100x of float64 GMRES at the same iteration
+    imp = np.array(d64.implicit_history)
+    for c, rr in enumerate(ir.history[1:-1], start=1):
+        it = c * 50
+        if it <= len(imp):
+            assert rr <= 100 * imp[it - 1] + 1e-12, (c, rr, imp[it - 1])
+    # single precision alone stalls well above 1e-10
+    f32 = O.gmres(p.A, p.b.astype(np.float32), np.zeros(p.A.n), 50, 1e-10, 1500, dt=np.float32)
+    assert not f32.converged and 1e-8 < min(f32.history) < 1e-5
+
+
+# --- O6 polynomial ------------------------------------------------------------
+def check_poly_residual_identity():
+    A, D = _nonsym(40, 16)
+    v = rng(17).standard_normal(40)
+    for d in (0, 3, 7):
+        roots = O.poly_roots(A, d, v)
+        pv = O.poly_apply(A, roots, v)
+        lhs = np.linalg.norm(v - D @ pv)
+        K = np.empty((40, d + 1))
+        K[:, 0] = v
+        for c in range(1, d + 1):
+            K[:, c] = D @ K[:, c - 1]
+        AK = D @ K
+        c, *_ = np.linalg.lstsq(AK, v, rcond=None)
+        best = np.linalg.norm(v - AK @ c)
+        assert np.isclose(lhs, best, rtol=1e-8), (d, lhs, best)
+
+
+def check_poly_inverse_on_few_eigenvalues():
+    d = np.repeat([0.5, 1.0, 2.0, 4.0, 6.0], 4)
+    A = dense_csr(np.diag(d))
+    v = rng(18).uniform(0.5, 1.5, 20)
+    roots = O.poly_roots(A, 4, v)
+    pv = O.poly_apply(A, roots, v)
+    assert np.allclose(d * pv, v, rtol=1e-9), "p(A) != A^-1 with d+1 distinct eigenvalues"
+
+
+def check_poly_degree0():
+    A, D = _nonsym(25, 19)
+    v = rng(20).standard_normal(25)
+    roots = O.poly_roots(A, 0, v)
+    Av = D @ v
+    assert np.isclose(1.0 / roots[0].real, (Av @ v) / (Av @ Av), rtol=1e-12)
+    assert np.allclose(O.poly_apply(A, roots, v), (Av @ v) / (Av @ Av) * v, rtol=1e-12)
+
+
+def check_poly_spd_real_positive():
+    A = W.laplace2d(10)
+    v = rng(21).standard_normal(A.n)
+    roots = O.poly_roots(A, 10, v)
+    assert np.all(np.abs(roots.imag) < 1e-8) and np.all(roots.real > 0)
+    lam = W.laplacian_eigs_closed_form(10, 2)
+    assert np.all(roots.real < lam.max() * (1 + 1e-9)) and np.all(roots.real > lam.min() * (1 - 1e-9))
+
+
+def check_poly_roots_form_equals_monomial():
+    A, D = _nonsym(8, 22)
+    v = rng(23).standard_normal(8)
+    d = 4
+    roots = O.poly_roots(A, d, v)
+    pi = np.real(np.poly(roots))                    # coefficients of prod (z - theta), highest first
+    pi = pi / pi[-1]                                 # normalise so pi(0) = 1
+    c = -pi[:-1]                                     # p(z) = (1 - pi(z))/z, highest power first
+    P = np.zeros_like(D)
+    for ck in c:                                     # Horner
+        P = P @ D + ck * np.eye(8)
+    assert np.allclose(O.poly_apply(A, roots, v), P @ v, rtol=1e-9, atol=1e-12)
+
+
+def check_leja_properties():
+    A, D = _nonsym(30, 24)
+    v = rng(25).standard_normal(30)
+    roots = O.poly_roots(A, 9, v)
+    assert np.isclose(abs(roots[0]), np.max(np.abs(roots)))
+    i = 0
+    while i < len(roots):
+        if roots[i].imag != 0:
+            assert roots[i].imag > 0 and roots[i + 1] == np.conj(roots[i])
+            i += 2
+        else:
+            i += 1
+    # harmonic Ritz values are the roots of the GMRES residual polynomial
+    # (brute force on a low degree, where the monomial Krylov basis is still
+    # well conditioned)
+    d = 4
+    roots = O.poly_roots(A, d, v)
+    K = np.empty((30, d + 1))
+    K[:, 0] = v
+    for c in range(1, d + 1):
+        K[:, c] = D @ K[:, c - 1]
+    c, *_ = np.linalg.lstsq(D @ K, v, rcond=None)
+    poly = np.concatenate([-c[::-1], [1.0]])          # 1 - z sum c_i z^i, highest first
+    ref = np.roots(poly)
+    assert np.allclose(np.sort_complex(ref), np.sort_complex(roots), rtol=1e-7, atol=1e-9)
+
+
+ALL_CHECKS = [
+    check_spmv_matches_dense, check_spmv_integer_exact, check_spmv_f32_bound,
+    check_arnoldi_orthogonal_and_hessenberg, check_arnoldi_equals_qr_of_krylov,
+    check_givens_matches_lstsq, check_back_substitute,
+    check_gmres_tiny_dense_solve, check_gmres_brute_force_minimisation,
+    check_gmres_finite_termination, check_gmres_config1_counts, check_gmres_ir_config1,
+    check_poly_residual_identity, check_poly_inverse_on_few_eigenvalues, check_poly_degree0,
+    check_poly_spd_real_positive, check_poly_roots_form_equals_monomial, check_leja_properties,
+]
+
+
+def check_arnoldi_f32_orthogonality():
+    # CGS2 keeps a float32 basis orthogonal to working accuracy even when the
+    # Krylov basis is ill conditioned ("twice is enough")
+    A = W.laplace2d(20)
+    v0 = rng(26).standard_normal(A.n)
+    V, H, k = O.arnoldi(A, v0, 40, np.float32)
+    orth = np.linalg.norm(V.astype(np.float64).T @ V.astype(np.float64) - np.eye(41))
+    assert orth < 2e-5, f"float32 ||V^T V - I|| = {orth}"
+
+
+ALL_CHECKS.append(check_arnoldi_f32_orthogonality)

@@ -1,0 +1,124 @@
+"""Plant plausible mistakes in the oracle (CPU only) and require the pins to catch them."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.krylov as K
+import oracle.poly as P
+import pins
+
+
+def _patch(monkeypatch, name, fn, modules=(oracle, K, P)):
+    for m in modules:
+        if hasattr(m, name):
+            monkeypatch.setattr(m, name, fn)
+
+
+def _fails(checks):
+    failed = []
+    for c in checks:
+        try:
+            c()
+        except Exception:  # AssertionError or a numerical error caused by the mutation
+            failed.append(c.__name__)
+    return failed
+
+
+def spmv_drop_last(A, x, dt=None):
+    dt = np.dtype(dt or x.dtype)
+    val = A.val.astype(dt)
+    x = np.asarray(x).astype(dt)
+    y = np.zeros(A.n, dt)
+    for r in range(A.n):
+        for k in range(A.row_ptr[r], A.row_ptr[r + 1] - 1):
+            y[r] += val[k] * x[A.col_idx[k]]
+    return y
+
+
+def spmv_row_index(A, x, dt=None):
+    dt = np.dtype(dt or x.dtype)
+    y = np.zeros(A.n, dt)
+    for r in range(A.n):
+        for k in range(A.row_ptr[r], A.row_ptr[r + 1]):
+            y[r] += A.val[k] * x[r]
+    return y
+
+
+def cgs_single_pass(V, j, w):
+    Vj = V[:, :j]
+    h1 = Vj.T @ w
+    w = w - Vj @ h1
+    return w, h1, np.zeros_like(h1), np.sqrt(w @ w)
+
+
+def cgs2_stale_w(V, j, w):
+    Vj = V[:, :j]
+    h1 = Vj.T @ w
+    w1 = w - Vj @ h1
+    h2 = Vj.T @ w            # mistake: dots against the unupdated vector
+    w2 = w1 - Vj @ h2
+    return w2, h1, h2, np.sqrt(w2 @ w2)
+
+
+def givens_wrong_sign(h, cs, sn, g, j):
+    for i in range(j):
+        hi, hi1 = h[i], h[i + 1]
+        h[i] = cs[i] * hi + sn[i] * hi1
+        h[i + 1] = sn[i] * hi + cs[i] * hi1          # mistake: sign of the sine
+    a, b = h[j], h[j + 1]
+    rho = float(np.hypot(a, b))
+    cs[j], sn[j] = (1.0, 0.0) if rho == 0 else (a / rho, b / rho)
+    h[j], h[j + 1] = rho, 0.0
+    g[j + 1] = -sn[j] * g[j]
+    g[j] = cs[j] * g[j]
+    return abs(g[j + 1])
+
+
+def backsolve_transposed(R, g):
+    k = R.shape[0]
+    y = np.zeros(k)
+    for i in range(k - 1, -1, -1):
+        s = g[i]
+        for c in range(i + 1, k):
+            s -= R[c, i] * y[c]                      # mistake: transposed operand
+        y[i] = s / R[i, i]
+    return y
+
+
+def poly_apply_half_a(A, roots, x, dt=np.float64):
+    r = np.array([complex(z.real * (0.5 if z.imag != 0 else 1.0), z.imag) for z in roots])
+    return _orig_poly_apply(A, r, x, dt)
+
+
+def harmonic_unsquared(H, k):
+    Hk = H[:k, :k].copy()
+    ek = np.zeros(k)
+    ek[-1] = 1.0
+    f = np.linalg.solve(Hk.T, ek)
+    Hk[:, k - 1] += H[k, k - 1] * f                  # mistake: h_{k+1,k} not squared
+    return np.linalg.eigvals(Hk)
+
+
+_orig_poly_apply = P.poly_apply
+
+MUTATIONS = {
+    "spmv_drop_last": ("spmv", spmv_drop_last),
+    "spmv_row_index": ("spmv", spmv_row_index),
+    "cgs_single_pass": ("cgs2", cgs_single_pass),
+    "cgs2_stale_w": ("cgs2", cgs2_stale_w),
+    "givens_wrong_sign": ("apply_givens_column", givens_wrong_sign),
+    "backsolve_transposed": ("back_substitute", backsolve_transposed),
+    "poly_apply_half_a": ("poly_apply", poly_apply_half_a),
+    "harmonic_unsquared": ("harmonic_ritz_values", harmonic_unsquared),
+}
+
+FAST_CHECKS = [c for c in pins.ALL_CHECKS if c.__name__ not in
+               ("check_gmres_config1_counts", "check_gmres_ir_config1", "check_spmv_integer_exact")]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(monkeypatch, name):
+    attr, fn = MUTATIONS[name]
+    _patch(monkeypatch, attr, fn)
+    failed = _fails(FAST_CHECKS)
+    assert failed, f"mutation {name} passed every pin"
