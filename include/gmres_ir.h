@@ -1,0 +1,191 @@
+/*
+ * gmres_ir.h — C ABI of the MI355X GMRES / GMRES-IR hot path (libgmresir.so).
+ *
+ * The problem is the one of Alg. 1: solve A x = b for a real n x n sparse A,
+ * given b, an initial guess x0 and a relative residual tolerance tol, with
+ * convergence meaning ||b - A x||_2 / ||b||_2 <= tol (§III-A).  GMRES(m) is
+ * restarted every m iterations (§III-A); GMRES-IR (Alg. 2, §III-B) runs the
+ * inner GMRES(m) in float32 on a float32 copy of A and keeps the residual and
+ * the solution update in float64.  Right preconditioning with a GMRES
+ * polynomial of degree d is §III-D.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named "device" are HIP device memory owned by the caller; the
+ *    library never allocates device memory.  Solver scratch comes from one
+ *    caller-provided workspace whose size gmres_workspace_bytes() returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    spmv, cgs2_orth and poly_prec_apply only enqueue work; the solvers and
+ *    poly_prec_setup synchronise `stream` before returning.
+ *  - Arguments are checked before anything is enqueued.  A negative status
+ *    means nothing usable was produced; gmr_last_error() then returns a
+ *    message (thread-local, valid until the next call on the thread).
+ *    A positive status from a solver means x holds the best iterate found.
+ *  - Index arrays are int32 (row_ptr has n+1 entries, col_idx nnz entries,
+ *    columns ascending within a row is not required); values are float32 or
+ *    float64 as `dtype` says.
+ *  - Dense vectors are contiguous; the Krylov basis V is column-major with
+ *    leading dimension ldv >= n.
+ */
+#ifndef GMRES_IR_H
+#define GMRES_IR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { GMR_F32 = 0, GMR_F64 = 1 } gmr_dtype;
+
+typedef enum {
+  GMR_OK = 0,
+  GMR_NOT_CONVERGED = 1,     /* max_iters / max_cycles reached; x = last iterate        */
+  GMR_STAGNATED = 2,         /* no residual decrease over `stagnation_cycles` restarts */
+  GMR_ERR_INVALID = -1,      /* bad argument (null pointer, size, dtype mismatch, ...)   */
+  GMR_ERR_HIP = -2,          /* a HIP call failed                                        */
+  GMR_ERR_WORKSPACE = -3,    /* workspace smaller than gmres_workspace_bytes()           */
+  GMR_ERR_NONFINITE = -4,    /* NaN/Inf in b, in a residual norm or in the Hessenberg    */
+  GMR_ERR_UNSUPPORTED = -5   /* parameter outside what this build supports               */
+} gmr_status;
+
+/* CSR matrix; all three arrays are device pointers. */
+typedef struct {
+  int32_t n;                 /* rows = columns, > 0                */
+  int32_t nnz;               /* row_ptr[n] - row_ptr[0], >= 0      */
+  const int32_t* row_ptr;    /* n+1 entries, row_ptr[0] == 0       */
+  const int32_t* col_idx;    /* nnz entries in [0, n)              */
+  const void* val;           /* nnz values of type `dtype`         */
+  int32_t dtype;             /* gmr_dtype                          */
+} gmr_csr;
+
+/* Profiling selector: the solver brackets every launch of one kernel family
+ * with HIP events and reports their summed duration and algorithmic bytes. */
+typedef enum {
+  GMR_PROF_NONE = 0, GMR_PROF_SPMV = 1, GMR_PROF_CGS_DOTS = 2, GMR_PROF_CGS_UPDATE_DOTS = 3,
+  GMR_PROF_CGS_UPDATE_NORM = 4, GMR_PROF_POLY_STEP = 5, GMR_PROF_RESIDUAL = 6
+} gmr_prof_kernel;
+
+typedef struct {
+  int32_t restart;           /* m, 1 <= m <= 256 (§III-A "restart length")                 */
+  double tol;                /* relative residual tolerance, > 0                           */
+  int64_t max_iters;         /* cap on inner iterations (> 0)                              */
+  int32_t max_cycles;        /* cap on restarts, 0 = none                                  */
+  int32_t stagnation_cycles; /* GMRES-IR: give up after this many restarts without
+                                the residual decreasing by 1 %, 0 = never                  */
+  int32_t prof_kernel;       /* gmr_prof_kernel                                            */
+  int32_t reserved;
+} gmr_params;
+
+typedef struct {
+  int32_t status;            /* gmr_status                                                 */
+  int32_t cycles;            /* restarts performed                                         */
+  int64_t iters;             /* inner iterations performed (all cycles)                    */
+  double rel_res;            /* explicit ||b - A x|| / ||b|| in float64 at exit            */
+  double implicit_rel_res;   /* |g_{k+1}| * gamma / ||b|| of the last cycle                */
+  double seconds;            /* wall time of the solve (host clock, stream synchronised)   */
+  int32_t history_len;       /* entries written to `hist`                                  */
+  int32_t reserved;
+  double prof_ms;            /* summed duration of the profiled launches                   */
+  int64_t prof_launches;     /* number of profiled launches                                */
+  double prof_bytes;         /* summed algorithmic bytes of the profiled launches          */
+} gmr_result;
+
+typedef struct gmr_poly gmr_poly;  /* opaque, host-side: the roots of the polynomial */
+
+/* Workspace (bytes, device) needed by gmres_solve / gmres_ir_solve for a system of
+ * order n with the given parameters and working precision `dtype` (F64: plain
+ * float64 GMRES; F32: GMRES-IR, or a float32-only gmres_solve), with a
+ * polynomial preconditioner when `with_poly` != 0.  Also valid for cgs2_orth
+ * (with restart >= k) and for poly_prec_setup/poly_prec_apply. */
+size_t gmres_workspace_bytes(int32_t n, const gmr_params* params, int32_t dtype, int32_t with_poly);
+
+/* y = A x (§V-D: y_i = sum_k val[k] x[col[k]], summed in ascending k; products
+ * are rounded before they are added).  x, y: device, n entries of A's dtype,
+ * must not overlap.  Asynchronous. */
+gmr_status spmv(const gmr_csr* A, const void* x, void* y, void* stream);
+
+/* One CGS2 orthogonalisation step (Alg. 1 with the two classical Gram-Schmidt
+ * passes of §III-A): h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2,
+ * beta = ||w||, w /= beta.  V: device, n x k column-major, leading dim ldv.
+ * w: device, n entries, overwritten with the normalised vector (left as is
+ * when beta is 0).  h: device float64, k+1 entries: h[0..k-1] = h1 + h2 and
+ * h[k] = beta.  1 <= k <= 256.  dtype selects float32 or float64 data.
+ * ws: device workspace of gmres_workspace_bytes(n, {restart >= k}, dtype, 0)
+ * bytes.  Asynchronous. */
+gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t ldv, void* w,
+                     double* h, void* ws, size_t ws_bytes, void* stream);
+
+/* Build the GMRES-polynomial preconditioner p of degree `degree` (§III-D):
+ * run degree+1 Arnoldi (CGS2) steps on A from the device start vector v0
+ * (n entries of A's dtype, need not be normalised) in A's precision, take the
+ * harmonic Ritz values (the roots of the GMRES residual polynomial), order
+ * them by the modified Leja ordering and round them to A's precision.  A
+ * lucky breakdown after s steps lowers the degree to s-1.  0 <= degree <= 64.
+ * Synchronous; *out must be released with poly_prec_destroy. */
+gmr_status poly_prec_setup(const gmr_csr* A, int32_t degree, const void* v0, void* ws,
+                           size_t ws_bytes, gmr_poly** out, void* stream);
+
+/* y = p(A) x with the roots of P (exactly degree products with A).  A must
+ * have the dtype P was built for; x, y: device, n entries, must not overlap.
+ * ws as for poly_prec_setup.  Asynchronous. */
+gmr_status poly_prec_apply(const gmr_poly* P, const gmr_csr* A, const void* x, void* y, void* ws,
+                           size_t ws_bytes, void* stream);
+
+void poly_prec_destroy(gmr_poly* P);
+
+/* The (s+1) x s Hessenberg matrix of the Arnoldi run that built P (s = degree+1),
+ * column-major with leading dimension s+1, into the host array H. */
+gmr_status poly_prec_hessenberg(const gmr_poly* P, double* H);
+
+/* Degree d of P and its d+1 roots (float64 copies of the rounded values, Leja order). */
+int32_t poly_prec_degree(const gmr_poly* P);
+gmr_status poly_prec_roots(const gmr_poly* P, double* re, double* im);
+
+/* Restarted GMRES(m) in A's precision (Alg. 1 with CGS2): the implicit residual
+ * is tested after every iteration and convergence is confirmed by the
+ * explicit residual at the end of the cycle.  b: device, n entries; x: device,
+ * n entries, holds x0 on entry and the solution on exit (both of A's dtype).
+ * P: optional right preconditioner of the same dtype (NULL = none).
+ * hist: optional host array of max_cycles+1 (or 4096 when max_cycles is 0)
+ * float64 explicit relative residuals, one per restart, starting with x0's.
+ * Synchronous. */
+gmr_status gmres_solve(const gmr_csr* A, const gmr_poly* P, const void* b, void* x,
+                       const gmr_params* params, void* ws, size_t ws_bytes, gmr_result* result,
+                       double* hist, void* stream);
+
+/* GMRES-IR (Alg. 2): r = b - A64 x in float64; each cycle solves A u = r by
+ * exactly m float32 GMRES iterations on A32 (only a breakdown ends a cycle
+ * early) and adds u to x in float64, until ||r|| / ||b|| <= tol.
+ * A64: float64 matrix; A32: the same pattern with float32 values (see
+ * csr_values_to_f32).  P: optional float32 right preconditioner built on A32.
+ * b, x: device float64.  hist as for gmres_solve.  Synchronous. */
+gmr_status gmres_ir_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly* P,
+                          const double* b, double* x, const gmr_params* params, void* ws,
+                          size_t ws_bytes, gmr_result* result, double* hist, void* stream);
+
+/* out[k] = (float) in[k], round to nearest even; in, out: device.  Asynchronous. */
+gmr_status csr_values_to_f32(const double* in, float* out, int64_t count, void* stream);
+
+/* Eigenvalues of a k x k upper Hessenberg matrix (host, column-major, ld k) by
+ * the Francis double-shift QR iteration; host only, used by poly_prec_setup.
+ * re, im: host, k entries.  Returns GMR_ERR_NONFINITE if it fails to converge. */
+gmr_status gmr_hessenberg_eigvals(int32_t k, const double* H, double* re, double* im);
+
+/* Harmonic Ritz values of a k-step Arnoldi run (host): the eigenvalues of
+ * H_k + h_{k+1,k}^2 f e_k^T with H_k^T f = e_k, i.e. the roots of the k-step
+ * GMRES residual polynomial (§III-D).  H: host, column-major (k+1) x k with
+ * leading dimension ldh >= k+1; re, im: host, k entries. */
+gmr_status gmr_harmonic_ritz(int32_t k, const double* H, int32_t ldh, double* re, double* im);
+
+/* Modified Leja ordering of k values (host, in place): largest modulus first,
+ * then the value maximising the sum of log distances to those chosen;
+ * complex-conjugate pairs adjacent, positive imaginary part first. */
+gmr_status gmr_leja_order(int32_t k, double* re, double* im);
+
+const char* gmr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMRES_IR_H */

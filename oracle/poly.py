@@ -43,16 +43,16 @@ def leja_order(theta: np.ndarray) -> np.ndarray:
     out = []
 
     def take(i):
-        t = rest.pop(i)
-        if t.imag != 0.0:
-            t = complex(t.real, abs(t.imag))
-            out.append(t)
-            # remove the matching conjugate
-            j = min(range(len(rest)), key=lambda q: abs(rest[q] - t.conjugate()))
+        t0 = rest.pop(i)
+        if t0.imag != 0.0:
+            # remove the matching conjugate of the value taken
+            j = min(range(len(rest)), key=lambda q: abs(rest[q] - t0.conjugate()))
             rest.pop(j)
+            t = complex(t0.real, abs(t0.imag))
+            out.append(t)
             out.append(t.conjugate())
         else:
-            out.append(t)
+            out.append(t0)
 
     i0 = max(range(len(rest)), key=lambda q: (abs(rest[q]), rest[q].imag))
     take(i0)

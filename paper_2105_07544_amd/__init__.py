@@ -1,0 +1,283 @@
+"""MI355X GMRES(m) / GMRES-IR hot path: Python binding of libgmresir.so.
+
+Torch supplies device memory and the current HIP stream; every step of the
+solvers runs in the library's HIP kernels.  The names follow the C ABI in
+include/gmres_ir.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _capi
+from ._capi import GMR_F32, GMR_F64, GmresError, PROF, check
+
+__all__ = ["DeviceCSR", "Poly", "SolveResult", "workspace_bytes", "alloc_workspace", "spmv",
+           "cgs2_orth", "poly_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve",
+           "hessenberg_eigvals", "harmonic_ritz", "leja_order", "GmresError", "GMR_F32", "GMR_F64", "lib"]
+
+
+def lib():
+    return _capi.load()
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.float64:
+        return GMR_F64
+    if t == torch.float32:
+        return GMR_F32
+    raise ValueError(f"unsupported dtype {t}")
+
+
+class DeviceCSR:
+    """A CSR matrix whose arrays live in device memory (int32 indices)."""
+
+    def __init__(self, row_ptr, col_idx, val, device="cuda"):
+        self.row_ptr = torch.as_tensor(np.asarray(row_ptr) if not torch.is_tensor(row_ptr) else row_ptr,
+                                       dtype=torch.int32).to(device).contiguous()
+        self.col_idx = torch.as_tensor(np.asarray(col_idx) if not torch.is_tensor(col_idx) else col_idx,
+                                       dtype=torch.int32).to(device).contiguous()
+        v = val if torch.is_tensor(val) else torch.from_numpy(np.ascontiguousarray(val))
+        if v.dtype not in (torch.float32, torch.float64):
+            v = v.to(torch.float64)
+        self.val = v.to(device).contiguous()
+        self.n = int(self.row_ptr.numel()) - 1
+        self.nnz = int(self.col_idx.numel())
+        self.device = self.val.device
+
+    @classmethod
+    def from_host(cls, A, device="cuda"):
+        """From any object with n, row_ptr, col_idx, val (numpy)."""
+        return cls(A.row_ptr, A.col_idx, A.val, device)
+
+    @property
+    def dtype(self) -> int:
+        return _dtype_code(self.val.dtype)
+
+    def struct(self) -> _capi.gmr_csr:
+        return _capi.gmr_csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                             self.val.data_ptr(), self.dtype)
+
+    def to_f32(self) -> "DeviceCSR":
+        """Float32 copy of the values (round to nearest) by the library's cast kernel;
+        the index arrays are shared."""
+        out = DeviceCSR.__new__(DeviceCSR)
+        out.row_ptr, out.col_idx, out.n, out.nnz, out.device = (self.row_ptr, self.col_idx, self.n,
+                                                                 self.nnz, self.device)
+        out.val = torch.empty(self.nnz, dtype=torch.float32, device=self.device)
+        if self.val.dtype == torch.float32:
+            out.val.copy_(self.val)
+        else:
+            check(lib().csr_values_to_f32(_ptr(self.val), _ptr(out.val), self.nnz, _stream(self.device)))
+        return out
+
+
+def workspace_bytes(n: int, restart: int, dtype: int, with_poly: bool = False) -> int:
+    p = _capi.gmr_params(restart, 1e-10, 1, 0, 0, 0, 0)
+    nb = lib().gmres_workspace_bytes(n, C.byref(p), dtype, int(bool(with_poly)))
+    if nb == 0:
+        raise GmresError(-1, "invalid workspace query")
+    return int(nb)
+
+
+def alloc_workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def spmv(A: DeviceCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x (asynchronous on the current stream)."""
+    if y is None:
+        y = torch.empty(A.n, dtype=A.val.dtype, device=A.device)
+    st = A.struct()
+    check(lib().spmv(C.byref(st), _ptr(x), _ptr(y), _stream(A.device)))
+    return y
+
+
+def cgs2_orth(V: torch.Tensor, k: int, w: torch.Tensor, ws: Optional[torch.Tensor] = None,
+              ldv: Optional[int] = None) -> torch.Tensor:
+    """Orthogonalise w against the first k columns of V (column-major n x >=k,
+    given as a (cols, ldv) row-major tensor) by CGS2 and normalise it in place.
+    Returns h (float64, k+1): h[:k] = h1 + h2, h[k] = ||w|| before normalising."""
+    n = w.numel()
+    ld = ldv if ldv is not None else V.shape[-1]
+    dt = _dtype_code(w.dtype)
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(n, max(k, 1), dt), w.device)
+    h = torch.empty(k + 1, dtype=torch.float64, device=w.device)
+    check(lib().cgs2_orth(dt, n, k, _ptr(V), ld, _ptr(w), _ptr(h), _ptr(ws), ws.numel(),
+                          _stream(w.device)))
+    return h
+
+
+class Poly:
+    """Handle of a GMRES polynomial built by poly_prec_setup."""
+
+    def __init__(self, handle: C.c_void_p, dtype: int):
+        self._h = handle
+        self.dtype = dtype
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def degree(self) -> int:
+        return int(lib().poly_prec_degree(self._h))
+
+    def roots(self) -> np.ndarray:
+        k = self.degree + 1
+        re = np.zeros(k)
+        im = np.zeros(k)
+        check(lib().poly_prec_roots(self._h, re.ctypes.data_as(C.c_void_p), im.ctypes.data_as(C.c_void_p)))
+        return re + 1j * im
+
+    def hessenberg(self) -> np.ndarray:
+        """(s+1) x s Hessenberg matrix of the Arnoldi run that built the polynomial."""
+        s = self.degree + 1
+        H = np.zeros((s + 1) * s)
+        check(lib().poly_prec_hessenberg(self._h, H.ctypes.data_as(C.c_void_p)))
+        return H.reshape(s, s + 1).T.copy()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().poly_prec_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def poly_prec_setup(A: DeviceCSR, degree: int, v0: torch.Tensor, ws: Optional[torch.Tensor] = None) -> Poly:
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(A.n, degree + 1, A.dtype, True), A.device)
+    out = C.c_void_p()
+    st = A.struct()
+    check(lib().poly_prec_setup(C.byref(st), degree, _ptr(v0), _ptr(ws), ws.numel(), C.byref(out),
+                                _stream(A.device)))
+    return Poly(out, A.dtype)
+
+
+def poly_prec_apply(P: Poly, A: DeviceCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    if y is None:
+        y = torch.empty_like(x)
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(A.n, 1, A.dtype, True), A.device)
+    st = A.struct()
+    check(lib().poly_prec_apply(P.handle, C.byref(st), _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                _stream(A.device)))
+    return y
+
+
+@dataclass
+class SolveResult:
+    status: int
+    status_name: str
+    iters: int
+    cycles: int
+    rel_res: float
+    implicit_rel_res: float
+    seconds: float
+    history: List[float] = field(default_factory=list)
+    prof_ms: float = 0.0
+    prof_launches: int = 0
+    prof_bytes: float = 0.0
+
+    @property
+    def converged(self) -> bool:
+        return self.status == 0
+
+
+def _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof):
+    return _capi.gmr_params(int(restart), float(tol), int(max_iters), int(max_cycles),
+                            int(stagnation_cycles), PROF[prof] if isinstance(prof, str) else int(prof), 0)
+
+
+def _result(res: _capi.gmr_result, hist: np.ndarray) -> SolveResult:
+    return SolveResult(res.status, _capi.STATUS.get(res.status, str(res.status)), int(res.iters),
+                       int(res.cycles), float(res.rel_res), float(res.implicit_rel_res),
+                       float(res.seconds), list(hist[: res.history_len]), float(res.prof_ms),
+                       int(res.prof_launches), float(res.prof_bytes))
+
+
+def gmres_solve(A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None, *, restart: int = 50,
+                tol: float = 1e-10, max_iters: int = 100000, max_cycles: int = 0,
+                P: Optional[Poly] = None, ws: Optional[torch.Tensor] = None, prof="none"):
+    """Restarted GMRES(m) in A's precision.  x (x0, updated in place) defaults to 0."""
+    if x is None:
+        x = torch.zeros_like(b)
+    prm = _params(restart, tol, max_iters, max_cycles, 0, prof)
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(A.n, restart, A.dtype, P is not None), A.device)
+    cap = max_cycles + 1 if max_cycles > 0 else 4096
+    hist = np.zeros(cap)
+    res = _capi.gmr_result()
+    st = A.struct()
+    status = lib().gmres_solve(C.byref(st), P.handle if P else None, _ptr(b), _ptr(x), C.byref(prm),
+                               _ptr(ws), ws.numel(), C.byref(res), hist.ctypes.data_as(C.c_void_p),
+                               _stream(A.device))
+    check(status)
+    return x, _result(res, hist)
+
+
+def gmres_ir_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None, *,
+                   restart: int = 50, tol: float = 1e-10, max_iters: int = 100000, max_cycles: int = 0,
+                   stagnation_cycles: int = 0, P: Optional[Poly] = None,
+                   ws: Optional[torch.Tensor] = None, prof="none"):
+    """GMRES-IR: float32 inner GMRES(m) on A32, float64 residual and update on A64."""
+    if x is None:
+        x = torch.zeros_like(b)
+    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof)
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(A64.n, restart, GMR_F32, P is not None), A64.device)
+    cap = max_cycles + 1 if max_cycles > 0 else 4096
+    hist = np.zeros(cap)
+    res = _capi.gmr_result()
+    s64, s32 = A64.struct(), A32.struct()
+    status = lib().gmres_ir_solve(C.byref(s64), C.byref(s32), P.handle if P else None, _ptr(b), _ptr(x),
+                                  C.byref(prm), _ptr(ws), ws.numel(), C.byref(res),
+                                  hist.ctypes.data_as(C.c_void_p), _stream(A64.device))
+    check(status)
+    return x, _result(res, hist)
+
+
+def hessenberg_eigvals(H: np.ndarray) -> np.ndarray:
+    """Eigenvalues of an upper Hessenberg matrix (host routine of the library)."""
+    k = H.shape[0]
+    Hc = np.asfortranarray(H, dtype=np.float64)
+    re = np.zeros(k)
+    im = np.zeros(k)
+    check(lib().gmr_hessenberg_eigvals(k, Hc.ctypes.data_as(C.c_void_p), re.ctypes.data_as(C.c_void_p),
+                                       im.ctypes.data_as(C.c_void_p)))
+    return re + 1j * im
+
+
+def harmonic_ritz(H: np.ndarray) -> np.ndarray:
+    """Harmonic Ritz values of a (k+1) x k Hessenberg matrix (host routine of the library)."""
+    k = H.shape[1]
+    Hc = np.asfortranarray(H, dtype=np.float64)
+    re = np.zeros(k)
+    im = np.zeros(k)
+    check(lib().gmr_harmonic_ritz(k, Hc.ctypes.data_as(C.c_void_p), k + 1, re.ctypes.data_as(C.c_void_p),
+                                  im.ctypes.data_as(C.c_void_p)))
+    return re + 1j * im
+
+
+def leja_order(z: np.ndarray) -> np.ndarray:
+    """Modified Leja ordering (host routine of the library)."""
+    re = np.ascontiguousarray(np.real(z), dtype=np.float64).copy()
+    im = np.ascontiguousarray(np.imag(z), dtype=np.float64).copy()
+    check(lib().gmr_leja_order(len(re), re.ctypes.data_as(C.c_void_p), im.ctypes.data_as(C.c_void_p)))
+    return re + 1j * im

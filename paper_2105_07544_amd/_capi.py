@@ -1,0 +1,106 @@
+"""ctypes declarations of libgmresir.so (include/gmres_ir.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmresir.so")
+
+GMR_F32, GMR_F64 = 0, 1
+STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", -1: "GMR_ERR_INVALID",
+          -2: "GMR_ERR_HIP", -3: "GMR_ERR_WORKSPACE", -4: "GMR_ERR_NONFINITE",
+          -5: "GMR_ERR_UNSUPPORTED"}
+PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_norm": 4,
+        "poly_step": 5, "residual": 6}
+
+# Every symbol include/gmres_ir.h declares.
+EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "poly_prec_apply",
+            "poly_prec_destroy", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
+            "gmres_ir_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
+            "gmr_last_error"]
+
+
+class gmr_csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p), ("dtype", C.c_int32)]
+
+
+class gmr_params(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("tol", C.c_double), ("max_iters", C.c_int64),
+                ("max_cycles", C.c_int32), ("stagnation_cycles", C.c_int32),
+                ("prof_kernel", C.c_int32), ("reserved", C.c_int32)]
+
+
+class gmr_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("cycles", C.c_int32), ("iters", C.c_int64),
+                ("rel_res", C.c_double), ("implicit_rel_res", C.c_double),
+                ("seconds", C.c_double), ("history_len", C.c_int32), ("reserved", C.c_int32),
+                ("prof_ms", C.c_double), ("prof_launches", C.c_int64),
+                ("prof_bytes", C.c_double)]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the built library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2105_07544_amd.build.build()")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    st = C.c_int
+    lib.gmres_workspace_bytes.argtypes = [C.c_int32, C.POINTER(gmr_params), C.c_int32, C.c_int32]
+    lib.gmres_workspace_bytes.restype = C.c_size_t
+    lib.spmv.argtypes = [C.POINTER(gmr_csr), P, P, P]
+    lib.spmv.restype = st
+    lib.cgs2_orth.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, C.c_int64, P, P, P, C.c_size_t, P]
+    lib.cgs2_orth.restype = st
+    lib.poly_prec_setup.argtypes = [C.POINTER(gmr_csr), C.c_int32, P, P, C.c_size_t, C.POINTER(P), P]
+    lib.poly_prec_setup.restype = st
+    lib.poly_prec_apply.argtypes = [P, C.POINTER(gmr_csr), P, P, P, C.c_size_t, P]
+    lib.poly_prec_apply.restype = st
+    lib.poly_prec_destroy.argtypes = [P]
+    lib.poly_prec_destroy.restype = None
+    lib.poly_prec_degree.argtypes = [P]
+    lib.poly_prec_degree.restype = C.c_int32
+    lib.poly_prec_roots.argtypes = [P, P, P]
+    lib.poly_prec_roots.restype = st
+    lib.gmres_solve.argtypes = [C.POINTER(gmr_csr), P, P, P, C.POINTER(gmr_params), P, C.c_size_t,
+                                C.POINTER(gmr_result), P, P]
+    lib.gmres_solve.restype = st
+    lib.gmres_ir_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P,
+                                   C.POINTER(gmr_params), P, C.c_size_t, C.POINTER(gmr_result), P, P]
+    lib.gmres_ir_solve.restype = st
+    lib.csr_values_to_f32.argtypes = [P, P, C.c_int64, P]
+    lib.csr_values_to_f32.restype = st
+    lib.gmr_hessenberg_eigvals.argtypes = [C.c_int32, P, P, P]
+    lib.gmr_hessenberg_eigvals.restype = st
+    lib.poly_prec_hessenberg.argtypes = [P, P]
+    lib.poly_prec_hessenberg.restype = st
+    lib.gmr_harmonic_ritz.argtypes = [C.c_int32, P, C.c_int32, P, P]
+    lib.gmr_harmonic_ritz.restype = st
+    lib.gmr_leja_order.argtypes = [C.c_int32, P, P]
+    lib.gmr_leja_order.restype = st
+    lib.gmr_last_error.argtypes = []
+    lib.gmr_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class GmresError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int) -> int:
+    if status < 0:
+        raise GmresError(status, load().gmr_last_error().decode())
+    return status

@@ -1,0 +1,789 @@
+// Host orchestration and C ABI of the GMRES(m) / GMRES-IR hot path.
+//
+// One solver template drives both methods:
+//   * plain GMRES(m) (Alg. 1 with CGS2, §III-A): inner = outer precision, the
+//     implicit residual ends a cycle early, the explicit one confirms;
+//   * GMRES-IR (Alg. 2, §III-B): float32 inner cycles of exactly m steps on a
+//     float32 copy of A, float64 residual and solution update.
+// Per inner iteration the stream receives: [poly steps] + SpMV (with the
+// normalisation of v_j fused in), CGS2 dots, update+dots, update+norm with the
+// float64 Givens step in its last block.  The host synchronises once per
+// restart to read gamma = ||b - A x|| and the cycle status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gmres_ir.h"
+#include "host_common.hpp"
+#include "kernels.hpp"
+
+namespace gmr {
+
+std::string& last_error() {
+  static thread_local std::string msg;
+  return msg;
+}
+
+#define GMR_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(GMR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+#define GMR_TRY(expr)               \
+  do {                              \
+    gmr_status s_ = (expr);         \
+    if (s_ != GMR_OK) return s_;    \
+  } while (0)
+
+static inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+static inline size_t dsize(int dtype) { return dtype == GMR_F64 ? 8 : 4; }
+static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Grid of the SpMV-type kernels (one block per 256 rows).
+static inline int spmv_grid(int n) { return ceil_div(n, kSpmvRows); }
+// Grid of the CGS dot kernels: at most kMaxRedBlocks blocks (4 per CU); each
+// writes one row of column partials.
+static inline int dots_grid(int n) { return std::max(1, std::min(ceil_div(ceil_div(n, kWave), kWavesPerBlock), kMaxRedBlocks)); }
+// Grid of the streaming kernels.
+static inline int stream_grid(int n) { return std::max(1, std::min(ceil_div(n, kBlock), kMaxRedBlocks)); }
+
+// ---------------------------------------------------------------------------
+// Workspace.  A fixed "small" region (reduction partials, the
+// Hessenberg problem, status) followed by the n-sized vectors.
+// ---------------------------------------------------------------------------
+struct Small {
+  size_t partial, H, Hraw, cs, sn, g, y, h1d, h2d, h1t, h2t, inv_beta, status, end;
+};
+
+static Small small_layout(int n) {
+  Small L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+  const size_t npart = std::max<size_t>((size_t)kMaxRedBlocks * kPartPitch, (size_t)spmv_grid(n));
+  L.partial = take(npart * 8);
+  const size_t hsz = (size_t)(kMaxCols + 1) * kMaxCols * 8;
+  L.H = take(hsz);
+  L.Hraw = take(hsz);
+  L.cs = take(kMaxCols * 8);
+  L.sn = take(kMaxCols * 8);
+  L.g = take((kMaxCols + 1) * 8);
+  L.y = take(kMaxCols * 8);
+  L.h1d = take(kMaxCols * 8);
+  L.h2d = take(kMaxCols * 8);
+  L.h1t = take(kMaxCols * 8);
+  L.h2t = take(kMaxCols * 8);
+  L.inv_beta = take(8 * 8);
+  L.status = take(sizeof(Status));
+  L.end = o;
+  return L;
+}
+
+struct Big {
+  size_t V, W0, W1, R, U, P0, P1, Tt, Z, end;
+  int64_t ldv;
+};
+
+// m: restart; s: inner element size; so: outer element size.
+static Big big_layout(size_t base, int n, int m, size_t s, size_t so, bool poly) {
+  Big L;
+  size_t o = base;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+  L.ldv = (int64_t)align_up((size_t)n, 64);
+  L.V = take((size_t)(m + 1) * L.ldv * s);
+  L.W0 = take((size_t)n * s);
+  L.W1 = take((size_t)n * s);
+  L.R = take((size_t)n * so);
+  L.U = take((size_t)n * s);
+  L.P0 = L.P1 = L.Tt = L.Z = 0;
+  if (poly) {
+    L.P0 = take((size_t)n * s);
+    L.P1 = take((size_t)n * s);
+    L.Tt = take((size_t)n * s);
+    L.Z = take((size_t)n * s);
+  }
+  L.end = o;
+  return L;
+}
+
+struct Ws {
+  char* base;
+  Small S;
+  double* partial() const { return (double*)(base + S.partial); }
+  Status* status() const { return (Status*)(base + S.status); }
+  CycleState cycle(int m) const {
+    CycleState c;
+    c.H = (double*)(base + S.H);
+    c.Hraw = (double*)(base + S.Hraw);
+    c.cs = (double*)(base + S.cs);
+    c.sn = (double*)(base + S.sn);
+    c.g = (double*)(base + S.g);
+    c.y = (double*)(base + S.y);
+    c.h1d = (double*)(base + S.h1d);
+    c.h2d = (double*)(base + S.h2d);
+    c.inv_beta = (double*)(base + S.inv_beta);
+    c.st = status();
+    c.ldh = m + 1;
+    return c;
+  }
+  template <class T> T* h1t() const { return (T*)(base + S.h1t); }
+  template <class T> T* h2t() const { return (T*)(base + S.h2t); }
+  template <class T> T* at(size_t off) const { return (T*)(base + off); }
+};
+
+// ---------------------------------------------------------------------------
+// Launch context: the stream plus the optional per-family event timing.
+// ---------------------------------------------------------------------------
+struct Prof {
+  int family = GMR_PROF_NONE;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  double bytes = 0.0;
+  int64_t launches = 0;
+};
+
+static Prof& prof_state() {
+  static thread_local Prof p;
+  return p;
+}
+
+struct Ctx {
+  hipStream_t s;
+  Prof* prof = nullptr;  // non-null while a solve is being profiled
+
+  gmr_status begin(int family) {
+    if (!prof || prof->family != family) return GMR_OK;
+    if (prof->used + 2 > prof->pool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        GMR_HIP(hipEventCreate(&e));
+        prof->pool.push_back(e);
+      }
+    }
+    GMR_HIP(hipEventRecord(prof->pool[prof->used], s));
+    return GMR_OK;
+  }
+  gmr_status end(int family, double bytes) {
+    if (!prof || prof->family != family) return GMR_OK;
+    GMR_HIP(hipEventRecord(prof->pool[prof->used + 1], s));
+    prof->used += 2;
+    prof->bytes += bytes;
+    prof->launches += 1;
+    return GMR_OK;
+  }
+};
+
+static gmr_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GMR_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return GMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks
+// ---------------------------------------------------------------------------
+static gmr_status check_csr(const gmr_csr* A, const char* who) {
+  if (!A) return fail(GMR_ERR_INVALID, std::string(who) + ": null matrix");
+  if (A->n <= 0) return fail(GMR_ERR_INVALID, std::string(who) + ": n must be > 0");
+  if (A->nnz < 0) return fail(GMR_ERR_INVALID, std::string(who) + ": nnz must be >= 0");
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))
+    return fail(GMR_ERR_INVALID, std::string(who) + ": null CSR array");
+  if (A->dtype != GMR_F32 && A->dtype != GMR_F64)
+    return fail(GMR_ERR_INVALID, std::string(who) + ": unknown dtype");
+  return GMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers (each returns a status; all are asynchronous)
+// ---------------------------------------------------------------------------
+template <class T>
+static double spmv_bytes(const gmr_csr* A) {
+  return (double)A->nnz * (4 + sizeof(T)) + (double)(A->n + 1) * 4 + 2.0 * A->n * sizeof(T);
+}
+
+template <class T>
+static gmr_status launch_spmv(Ctx& c, const gmr_csr* A, const T* x, const double* scale, T* vout,
+                              T* y, const int* done) {
+  GMR_TRY(c.begin(GMR_PROF_SPMV));
+  spmv_kernel<T><<<spmv_grid(A->n), kBlock, 0, c.s>>>(A->n, A->row_ptr, A->col_idx,
+                                                      (const T*)A->val, x, scale, vout, y, done);
+  GMR_TRY(check_launch("spmv_kernel"));
+  return c.end(GMR_PROF_SPMV, spmv_bytes<T>(A) + (vout ? (double)A->n * sizeof(T) : 0.0));
+}
+
+template <class T>
+static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* w,
+                              const Ws& ws, double* hd, T* ht, const int* done) {
+  GMR_TRY(c.begin(GMR_PROF_CGS_DOTS));
+  const int G = dots_grid(n);
+  double* part = ws.partial();
+  if (j <= 8)
+    cgs_dots_kernel<T, 8, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+  else if (j <= 16)
+    cgs_dots_kernel<T, 16, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+  else if (j <= 32)
+    cgs_dots_kernel<T, 32, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+  else if (j <= 64)
+    cgs_dots_kernel<T, 64, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+  else
+    cgs_dots_kernel<T, 64, 4><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+  GMR_TRY(check_launch("cgs_dots_kernel"));
+  GMR_TRY(c.end(GMR_PROF_CGS_DOTS, (double)(j + 1) * n * sizeof(T)));
+  finish_cols_kernel<T><<<j, kBlock, 0, c.s>>>(G, part, hd, ht, done);
+  return check_launch("finish_cols_kernel");
+}
+
+// Largest j for which the update and the second dots fuse (basis row in registers).
+template <class T> constexpr int fused_max() { return sizeof(T) == 4 ? 128 : 64; }
+
+template <class T>
+static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* hin,
+                                     T* w, const Ws& ws, double* hd, T* ht, const int* done) {
+  if (j > fused_max<T>()) {
+    // no room to keep the row in registers: update, then a separate dots pass
+    GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
+    cgs_update_kernel<T><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, done);
+    GMR_TRY(check_launch("cgs_update_kernel"));
+    GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, (double)(j + 2) * n * sizeof(T)));
+    return launch_dots<T>(c, n, j, V, ldv, w, ws, hd, ht, done);
+  }
+  GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
+  const int G = dots_grid(n);
+  double* part = ws.partial();
+#define GMR_UD(K) cgs_update_dots_kernel<T, K><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, part, done)
+  if (j <= 8) GMR_UD(8);
+  else if (j <= 16) GMR_UD(16);
+  else if (j <= 32) GMR_UD(32);
+  else if (j <= 64) GMR_UD(64);
+  else {
+    if constexpr (sizeof(T) == 4) GMR_UD(128);
+  }
+#undef GMR_UD
+  GMR_TRY(check_launch("cgs_update_dots_kernel"));
+  GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, (double)(j + 2) * n * sizeof(T)));
+  finish_cols_kernel<T><<<j, kBlock, 0, c.s>>>(G, part, hd, ht, done);
+  return check_launch("finish_cols_kernel");
+}
+
+template <class T, int MODE>
+static gmr_status launch_update_norm(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* hin,
+                                     T* w, const Ws& ws, CycleState cs, int last_jc,
+                                     double* hout, const int* done) {
+  GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_NORM));
+  const double thresh = sizeof(T) == 4 ? 1e3 * 1.1754943508222875e-38 : 0.0;
+  const int G = stream_grid(n);
+  cgs_update_norm_kernel<T><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, ws.partial(), done);
+  GMR_TRY(check_launch("cgs_update_norm_kernel"));
+  GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_NORM, (double)(j + 2) * n * sizeof(T)));
+  finish_norm_kernel<T, MODE><<<1, kBlock, 0, c.s>>>(G, ws.partial(), cs, j, last_jc, thresh, hout, done);
+  return check_launch("finish_norm_kernel");
+}
+
+// The three CGS2 passes on w against V[:, 0:j].
+template <class T, int MODE>
+static gmr_status cgs2_passes(Ctx& c, int n, int j, const T* V, int64_t ldv, T* w, const Ws& ws,
+                              CycleState cs, int last_jc, double* hout, const int* done) {
+  GMR_TRY(launch_dots<T>(c, n, j, V, ldv, w, ws, cs.h1d, ws.h1t<T>(), done));
+  GMR_TRY(launch_update_dots<T>(c, n, j, V, ldv, ws.h1t<T>(), w, ws, cs.h2d, ws.h2t<T>(), done));
+  return launch_update_norm<T, MODE>(c, n, j, V, ldv, ws.h2t<T>(), w, ws, cs, last_jc, hout, done);
+}
+
+}  // namespace gmr
+
+// ---------------------------------------------------------------------------
+// Polynomial object (host-side roots)
+// ---------------------------------------------------------------------------
+struct gmr_poly {
+  int32_t dtype;
+  std::vector<double> re, im;  // Leja-ordered roots, rounded to dtype's precision
+  std::vector<double> hess;    // Hessenberg matrix of the Arnoldi run, column-major
+  int32_t ldh = 0;             // its leading dimension (degree + 2)
+};
+
+namespace gmr {
+
+template <class T>
+static gmr_status poly_apply_impl(Ctx& c, const gmr_poly* P, const gmr_csr* A, const T* x, T* y,
+                                  T* P0, T* P1, T* Tt, const int* done) {
+  const int n = A->n;
+  const int k = (int)P->re.size();
+  const int G = spmv_grid(n);
+  const int GS = stream_grid(n);
+  const int* rp = A->row_ptr;
+  const int* ci = A->col_idx;
+  const T* val = (const T*)A->val;
+  const T* cur = x;
+  T* bufs[2] = {P0, P1};
+  int nb = 0;
+  bool first = true;
+  const double step_bytes = spmv_bytes<T>(A) + 3.0 * n * sizeof(T);
+  int i = 0;
+  while (i < k) {
+    if (P->im[i] == 0.0) {
+      const T cr = T(1.0 / P->re[i]);
+      if (i < k - 1) {
+        T* nxt = bufs[nb];
+        nb ^= 1;
+        GMR_TRY(c.begin(GMR_PROF_POLY_STEP));
+        if (first)
+          poly_real_kernel<T, true><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, cr, y, nxt, done);
+        else
+          poly_real_kernel<T, false><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, cr, y, nxt, done);
+        GMR_TRY(check_launch("poly_real_kernel"));
+        GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes));
+        cur = nxt;
+      } else {
+        if (first)
+          poly_real_last_kernel<T, true><<<GS, kBlock, 0, c.s>>>(n, cur, cr, y, done);
+        else
+          poly_real_last_kernel<T, false><<<GS, kBlock, 0, c.s>>>(n, cur, cr, y, done);
+        GMR_TRY(check_launch("poly_real_last_kernel"));
+      }
+      i += 1;
+    } else {
+      const double a = P->re[i], b = P->im[i];
+      const double mod2 = a * a + b * b;
+      const T c1 = T(2.0 * a / mod2), c2 = T(1.0 / mod2);
+      GMR_TRY(c.begin(GMR_PROF_POLY_STEP));
+      if (first)
+        poly_pair1_kernel<T, true><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, c1, c2, y, Tt, done);
+      else
+        poly_pair1_kernel<T, false><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, c1, c2, y, Tt, done);
+      GMR_TRY(check_launch("poly_pair1_kernel"));
+      GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes + (double)n * sizeof(T)));
+      if (i < k - 2) {
+        T* nxt = bufs[nb];
+        nb ^= 1;
+        GMR_TRY(c.begin(GMR_PROF_POLY_STEP));
+        poly_pair2_kernel<T><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, Tt, c1, c2, nxt, done);
+        GMR_TRY(check_launch("poly_pair2_kernel"));
+        GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes));
+        cur = nxt;
+      }
+      i += 2;
+    }
+    first = false;
+  }
+  return GMR_OK;
+}
+
+// Small kernel that seeds the Arnoldi state for the polynomial setup.
+__global__ void arnoldi_init_kernel(CycleState cs, const double* nrm) {
+  const double b0 = *nrm;
+  cs.g[0] = b0;
+  *cs.inv_beta = 1.0 / b0;
+  Status* st = cs.st;
+  st->beta0 = b0;
+  st->k = 0;
+  st->done = 0;
+  st->breakdown = 0;
+  st->nonfinite = !(b0 > 0.0) || !isfinite(b0);
+  st->stop_thresh = -1.0;
+  st->gamma = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// The solver
+// ---------------------------------------------------------------------------
+struct SolveArgs {
+  const gmr_csr* Ain;    // inner matrix (TI values)
+  const gmr_csr* Aout;   // outer matrix (TO values)
+  const gmr_poly* P;     // nullable, TI precision
+  const void* b;
+  void* x;
+  const gmr_params* prm;
+  void* ws;
+  size_t ws_bytes;
+  gmr_result* res;
+  double* hist;
+  hipStream_t stream;
+};
+
+static gmr_status check_params(const gmr_params* p) {
+  if (!p) return fail(GMR_ERR_INVALID, "null params");
+  if (p->restart < 1) return fail(GMR_ERR_INVALID, "restart must be >= 1");
+  if (p->restart > kMaxCols) return fail(GMR_ERR_UNSUPPORTED, "restart > 256 is not supported");
+  if (!(p->tol > 0.0)) return fail(GMR_ERR_INVALID, "tol must be > 0");
+  if (p->max_iters <= 0) return fail(GMR_ERR_INVALID, "max_iters must be > 0");
+  if (p->max_cycles < 0 || p->stagnation_cycles < 0) return fail(GMR_ERR_INVALID, "negative cycle cap");
+  return GMR_OK;
+}
+
+template <class TI, class TO>
+static gmr_status solve_impl(const SolveArgs& a) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const gmr_params& prm = *a.prm;
+  const int n = a.Aout->n;
+  const int m = prm.restart;
+  const bool implicit_stop = sizeof(TI) == sizeof(TO);  // plain GMRES
+  const bool poly = a.P != nullptr;
+  Ws ws{(char*)a.ws, small_layout(n)};
+  const Big B = big_layout(ws.S.end, n, m, sizeof(TI), sizeof(TO), poly);
+  if (!a.ws || a.ws_bytes < B.end)
+    return fail(GMR_ERR_WORKSPACE, "workspace too small: need " + std::to_string(B.end) + " bytes");
+
+  Ctx c{a.stream, nullptr};
+  Prof& pf = prof_state();
+  pf.family = prm.prof_kernel;
+  pf.used = 0;
+  pf.bytes = 0.0;
+  pf.launches = 0;
+  if (prm.prof_kernel != GMR_PROF_NONE) c.prof = &pf;
+
+  TI* V = ws.at<TI>(B.V);
+  TI* W[2] = {ws.at<TI>(B.W0), ws.at<TI>(B.W1)};
+  TO* r = ws.at<TO>(B.R);
+  TI* U = ws.at<TI>(B.U);
+  const TO* b = (const TO*)a.b;
+  TO* x = (TO*)a.x;
+  CycleState cs = ws.cycle(m);
+  Status* st_dev = ws.status();
+  const int* done = &st_dev->done;
+
+  norm2_kernel<TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, b, ws.partial());
+  GMR_TRY(check_launch("norm2_kernel"));
+  finish_norm2_kernel<<<1, kBlock, 0, c.s>>>(stream_grid(n), ws.partial(), &st_dev->bnorm);
+  GMR_TRY(check_launch("finish_norm2_kernel"));
+  auto residual = [&]() -> gmr_status {
+    GMR_TRY(c.begin(GMR_PROF_RESIDUAL));
+    residual_kernel<TO><<<spmv_grid(n), kBlock, 0, c.s>>>(n, a.Aout->row_ptr, a.Aout->col_idx,
+                                                         (const TO*)a.Aout->val, x, b, r,
+                                                         ws.partial());
+    GMR_TRY(check_launch("residual_kernel"));
+    GMR_TRY(c.end(GMR_PROF_RESIDUAL, spmv_bytes<TO>(a.Aout) + 2.0 * n * sizeof(TO)));
+    finish_residual_kernel<<<1, kBlock, 0, c.s>>>(spmv_grid(n), ws.partial(), st_dev);
+    return check_launch("finish_residual_kernel");
+  };
+  GMR_TRY(residual());
+  Status st;
+  GMR_HIP(hipMemcpyAsync(&st, st_dev, sizeof(Status), hipMemcpyDeviceToHost, c.s));
+  GMR_HIP(hipStreamSynchronize(c.s));
+
+  gmr_result R{};
+  R.status = GMR_NOT_CONVERGED;
+  const double bnorm = st.bnorm;
+  if (!std::isfinite(bnorm) || !std::isfinite(st.gamma)) return fail(GMR_ERR_NONFINITE, "non-finite b or x0");
+  const int hist_cap = prm.max_cycles > 0 ? prm.max_cycles + 1 : 4096;
+  auto push_hist = [&](double v) {
+    if (a.hist && R.history_len < hist_cap) a.hist[R.history_len] = v;
+    if (R.history_len < hist_cap) R.history_len++;
+  };
+  if (bnorm == 0.0) {
+    // b = 0: the solution is x = 0
+    GMR_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(TO), c.s));
+    GMR_HIP(hipStreamSynchronize(c.s));
+    R.status = GMR_OK;
+    R.rel_res = 0.0;
+    push_hist(0.0);
+    *a.res = R;
+    return GMR_OK;
+  }
+  double gamma = st.gamma;
+  push_hist(gamma / bnorm);
+  int64_t it = 0;
+  double best = gamma;
+  int since_best = 0;
+  gmr_status final_status = GMR_NOT_CONVERGED;
+  while (true) {
+    const double rel = gamma / bnorm;
+    if (!std::isfinite(rel)) { final_status = GMR_ERR_NONFINITE; fail(GMR_ERR_NONFINITE, "non-finite residual"); break; }
+    if (rel <= prm.tol) { final_status = GMR_OK; break; }
+    if (it >= prm.max_iters || (prm.max_cycles > 0 && R.cycles >= prm.max_cycles)) break;
+    if (prm.stagnation_cycles > 0 && R.cycles > 0) {
+      if (gamma < 0.99 * best) { best = gamma; since_best = 0; }
+      else if (++since_best >= prm.stagnation_cycles) { final_status = GMR_STAGNATED; break; }
+    }
+    // --- one cycle ---
+    start_cycle_kernel<TO, TI><<<stream_grid(n), kBlock, 0, c.s>>>(n, r, W[0], ws.partial(), st_dev);
+    GMR_TRY(check_launch("start_cycle_kernel"));
+    finish_start_cycle_kernel<TI><<<1, kBlock, 0, c.s>>>(stream_grid(n), ws.partial(), cs,
+                                                         implicit_stop ? prm.tol * bnorm : -1.0);
+    GMR_TRY(check_launch("finish_start_cycle_kernel"));
+    const int mc = (int)std::min<int64_t>(m, prm.max_iters - it);
+    int cur = 0;
+    for (int j = 0; j < mc; ++j) {
+      TI* vj = V + (size_t)j * B.ldv;
+      TI* wn = W[cur ^ 1];
+      if (poly) {
+        TI* Z = ws.at<TI>(B.Z);
+        scale_kernel<TI><<<stream_grid(n), kBlock, 0, c.s>>>(n, W[cur], cs.inv_beta, vj, done);
+        GMR_TRY(check_launch("scale_kernel"));
+        GMR_TRY(poly_apply_impl<TI>(c, a.P, a.Ain, vj, Z, ws.at<TI>(B.P0), ws.at<TI>(B.P1),
+                                    ws.at<TI>(B.Tt), done));
+        GMR_TRY(launch_spmv<TI>(c, a.Ain, Z, nullptr, nullptr, wn, done));
+      } else {
+        GMR_TRY(launch_spmv<TI>(c, a.Ain, W[cur], cs.inv_beta, vj, wn, done));
+      }
+      GMR_TRY((cgs2_passes<TI, kTailGivens>(c, n, j + 1, V, B.ldv, wn, ws, cs, mc - 1, nullptr, done)));
+      cur ^= 1;
+    }
+    if (poly) {
+      TI* Z = ws.at<TI>(B.Z);
+      solution_update_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, V, B.ldv, cs.y, st_dev, U, nullptr);
+      GMR_TRY(check_launch("solution_update_kernel"));
+      GMR_TRY(poly_apply_impl<TI>(c, a.P, a.Ain, U, Z, ws.at<TI>(B.P0), ws.at<TI>(B.P1),
+                                  ws.at<TI>(B.Tt), nullptr));
+      axpy_gamma_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, Z, st_dev, x);
+      GMR_TRY(check_launch("axpy_gamma_kernel"));
+    } else {
+      solution_update_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, V, B.ldv, cs.y, st_dev, nullptr, x);
+      GMR_TRY(check_launch("solution_update_kernel"));
+    }
+    const double gamma_cycle = gamma;
+    GMR_TRY(residual());
+    GMR_HIP(hipMemcpyAsync(&st, st_dev, sizeof(Status), hipMemcpyDeviceToHost, c.s));
+    GMR_HIP(hipStreamSynchronize(c.s));
+    it += st.k;
+    R.cycles += 1;
+    R.implicit_rel_res = st.res * gamma_cycle / bnorm;
+    gamma = st.gamma;
+    push_hist(gamma / bnorm);
+    if (st.nonfinite) { final_status = GMR_ERR_NONFINITE; fail(GMR_ERR_NONFINITE, "non-finite value in the Hessenberg problem"); break; }
+  }
+  GMR_HIP(hipStreamSynchronize(c.s));
+  const auto t_end = std::chrono::steady_clock::now();
+  R.status = final_status;
+  R.iters = it;
+  R.rel_res = gamma / bnorm;
+  R.seconds = std::chrono::duration<double>(t_end - t_start).count();
+  if (c.prof) {
+    double ms = 0.0;
+    for (size_t i = 0; i + 1 < pf.used; i += 2) {
+      float e = 0.f;
+      GMR_HIP(hipEventElapsedTime(&e, pf.pool[i], pf.pool[i + 1]));
+      ms += e;
+    }
+    R.prof_ms = ms;
+    R.prof_launches = pf.launches;
+    R.prof_bytes = pf.bytes;
+  }
+  *a.res = R;
+  return final_status;
+}
+
+}  // namespace gmr
+
+using namespace gmr;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* gmr_last_error(void) { return last_error().c_str(); }
+
+size_t gmres_workspace_bytes(int32_t n, const gmr_params* params, int32_t dtype, int32_t with_poly) {
+  if (n <= 0 || !params || params->restart < 1 || params->restart > kMaxCols) return 0;
+  if (dtype != GMR_F32 && dtype != GMR_F64) return 0;
+  const Small S = small_layout(n);
+  // the outer precision is float64 except for a float32-only solve; size for float64
+  const Big B = big_layout(S.end, n, params->restart, dsize(dtype), 8, with_poly != 0);
+  return B.end;
+}
+
+gmr_status spmv(const gmr_csr* A, const void* x, void* y, void* stream) {
+  GMR_TRY(check_csr(A, "spmv"));
+  if (!x || !y) return fail(GMR_ERR_INVALID, "spmv: null vector");
+  if (x == y) return fail(GMR_ERR_INVALID, "spmv: x and y must not overlap");
+  Ctx c{(hipStream_t)stream, nullptr};
+  if (A->dtype == GMR_F64)
+    return launch_spmv<double>(c, A, (const double*)x, nullptr, nullptr, (double*)y, nullptr);
+  return launch_spmv<float>(c, A, (const float*)x, nullptr, nullptr, (float*)y, nullptr);
+}
+
+gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t ldv, void* w,
+                     double* h, void* ws, size_t ws_bytes, void* stream) {
+  if (dtype != GMR_F32 && dtype != GMR_F64) return fail(GMR_ERR_INVALID, "cgs2_orth: unknown dtype");
+  if (n <= 0 || k < 1) return fail(GMR_ERR_INVALID, "cgs2_orth: need n > 0 and k >= 1");
+  if (k > kMaxCols) return fail(GMR_ERR_UNSUPPORTED, "cgs2_orth: k > 256 is not supported");
+  if (ldv < n) return fail(GMR_ERR_INVALID, "cgs2_orth: ldv < n");
+  if (!V || !w || !h) return fail(GMR_ERR_INVALID, "cgs2_orth: null pointer");
+  const Small S = small_layout(n);
+  if (!ws || ws_bytes < S.end) return fail(GMR_ERR_WORKSPACE, "cgs2_orth: workspace too small");
+  Ws W{(char*)ws, S};
+  Ctx c{(hipStream_t)stream, nullptr};
+  CycleState cs = W.cycle(k);
+  if (dtype == GMR_F64) {
+    GMR_TRY((cgs2_passes<double, kTailStandalone>(c, n, k, (const double*)V, ldv, (double*)w, W, cs, k - 1, h, nullptr)));
+    scale_kernel<double><<<stream_grid(n), kBlock, 0, c.s>>>(n, (const double*)w, cs.inv_beta, (double*)w, nullptr);
+  } else {
+    GMR_TRY((cgs2_passes<float, kTailStandalone>(c, n, k, (const float*)V, ldv, (float*)w, W, cs, k - 1, h, nullptr)));
+    scale_kernel<float><<<stream_grid(n), kBlock, 0, c.s>>>(n, (const float*)w, cs.inv_beta, (float*)w, nullptr);
+  }
+  return check_launch("scale_kernel");
+}
+
+gmr_status csr_values_to_f32(const double* in, float* out, int64_t count, void* stream) {
+  if (count < 0 || (count > 0 && (!in || !out))) return fail(GMR_ERR_INVALID, "csr_values_to_f32: bad arguments");
+  if (count == 0) return GMR_OK;
+  const int G = (int)std::min<int64_t>((count + kBlock - 1) / kBlock, 4096);
+  cast_f64_f32_kernel<<<G, kBlock, 0, (hipStream_t)stream>>>(count, in, out);
+  return check_launch("cast_f64_f32_kernel");
+}
+
+}  // extern "C"
+
+namespace gmr {
+template <class T>
+static gmr_status poly_setup_t(const gmr_csr* A, int32_t degree, const void* v0, void* wsp,
+                               size_t ws_bytes, gmr_poly** out, hipStream_t s) {
+  const int n = A->n;
+  const int k = degree + 1;
+  const Small S = small_layout(n);
+  const Big B = big_layout(S.end, n, k, sizeof(T), sizeof(T), false);
+  if (!wsp || ws_bytes < B.end) return fail(GMR_ERR_WORKSPACE, "poly_prec_setup: workspace too small");
+  Ws ws{(char*)wsp, S};
+  Ctx c{s, nullptr};
+  T* V = ws.at<T>(B.V);
+  T* W[2] = {ws.at<T>(B.W0), ws.at<T>(B.W1)};
+  CycleState cs = ws.cycle(k);
+  Status* st_dev = ws.status();
+  GMR_HIP(hipMemcpyAsync(W[0], v0, (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  double* nrm = cs.inv_beta + 1;
+  norm2_kernel<T><<<stream_grid(n), kBlock, 0, s>>>(n, W[0], ws.partial());
+  GMR_TRY(check_launch("norm2_kernel"));
+  finish_norm2_kernel<<<1, kBlock, 0, s>>>(stream_grid(n), ws.partial(), nrm);
+  GMR_TRY(check_launch("finish_norm2_kernel"));
+  arnoldi_init_kernel<<<1, 1, 0, s>>>(cs, nrm);
+  GMR_TRY(check_launch("arnoldi_init_kernel"));
+  const int* done = &st_dev->done;
+  int cur = 0;
+  for (int j = 0; j < k; ++j) {
+    GMR_TRY(launch_spmv<T>(c, A, W[cur], cs.inv_beta, V + (size_t)j * B.ldv, W[cur ^ 1], done));
+    GMR_TRY((cgs2_passes<T, kTailGivens>(c, n, j + 1, V, B.ldv, W[cur ^ 1], ws, cs, k - 1, nullptr, done)));
+    cur ^= 1;
+  }
+  Status st;
+  std::vector<double> Hraw((size_t)(k + 1) * k);
+  GMR_HIP(hipMemcpyAsync(&st, st_dev, sizeof(Status), hipMemcpyDeviceToHost, s));
+  GMR_HIP(hipMemcpyAsync(Hraw.data(), cs.Hraw, Hraw.size() * 8, hipMemcpyDeviceToHost, s));
+  GMR_HIP(hipStreamSynchronize(s));
+  if (st.nonfinite && !st.breakdown) return fail(GMR_ERR_NONFINITE, "poly_prec_setup: non-finite Arnoldi");
+  const int steps = st.k;
+  const int ld = k + 1;
+  if (steps < 1) return fail(GMR_ERR_NONFINITE, "poly_prec_setup: start vector is zero");
+  std::vector<double> re(steps), im(steps);
+  if (steps == k && !st.breakdown) {
+    GMR_TRY(gmr_harmonic_ritz(k, Hraw.data(), ld, re.data(), im.data()));
+  } else {
+    // lucky breakdown: the Ritz values of the s x s Hessenberg matrix are exact
+    std::vector<double> M((size_t)steps * steps);
+    for (int jcol = 0; jcol < steps; ++jcol)
+      for (int i = 0; i < steps; ++i)
+        M[(size_t)jcol * steps + i] = (i > jcol + 1) ? 0.0 : Hraw[(size_t)jcol * ld + i];
+    GMR_TRY(gmr_hessenberg_eigvals(steps, M.data(), re.data(), im.data()));
+  }
+  GMR_TRY(gmr_leja_order(steps, re.data(), im.data()));
+  gmr_poly* P = new gmr_poly;
+  P->dtype = A->dtype;
+  P->hess.assign(Hraw.begin(), Hraw.begin() + (size_t)steps * ld);
+  P->ldh = ld;
+  P->re.resize(steps);
+  P->im.resize(steps);
+  for (int i = 0; i < steps; ++i) {
+    P->re[i] = (double)(T)re[i];
+    P->im[i] = (double)(T)im[i];
+    if (P->re[i] == 0.0 && P->im[i] == 0.0) {
+      delete P;
+      return fail(GMR_ERR_NONFINITE, "poly_prec_setup: zero harmonic Ritz value");
+    }
+  }
+  *out = P;
+  return GMR_OK;
+}
+
+}  // namespace gmr
+
+extern "C" {
+
+gmr_status poly_prec_setup(const gmr_csr* A, int32_t degree, const void* v0, void* ws,
+                           size_t ws_bytes, gmr_poly** out, void* stream) {
+  GMR_TRY(check_csr(A, "poly_prec_setup"));
+  if (!v0 || !out) return fail(GMR_ERR_INVALID, "poly_prec_setup: null pointer");
+  if (degree < 0 || degree > 64) return fail(GMR_ERR_UNSUPPORTED, "poly_prec_setup: degree must be in [0, 64]");
+  *out = nullptr;
+  if (A->dtype == GMR_F64) return poly_setup_t<double>(A, degree, v0, ws, ws_bytes, out, (hipStream_t)stream);
+  return poly_setup_t<float>(A, degree, v0, ws, ws_bytes, out, (hipStream_t)stream);
+}
+
+gmr_status poly_prec_apply(const gmr_poly* P, const gmr_csr* A, const void* x, void* y, void* wsp,
+                           size_t ws_bytes, void* stream) {
+  if (!P) return fail(GMR_ERR_INVALID, "poly_prec_apply: null polynomial");
+  GMR_TRY(check_csr(A, "poly_prec_apply"));
+  if (A->dtype != P->dtype) return fail(GMR_ERR_INVALID, "poly_prec_apply: dtype of A and P differ");
+  if (!x || !y || x == y) return fail(GMR_ERR_INVALID, "poly_prec_apply: bad vectors");
+  const int n = A->n;
+  const Small S = small_layout(n);
+  const size_t s = dsize(A->dtype);
+  const size_t need = S.end + 3 * align_up((size_t)n * s, 256);
+  if (!wsp || ws_bytes < need) return fail(GMR_ERR_WORKSPACE, "poly_prec_apply: workspace too small");
+  char* base = (char*)wsp + S.end;
+  const size_t stride = align_up((size_t)n * s, 256);
+  Ctx c{(hipStream_t)stream, nullptr};
+  if (A->dtype == GMR_F64)
+    return poly_apply_impl<double>(c, P, A, (const double*)x, (double*)y, (double*)base,
+                                   (double*)(base + stride), (double*)(base + 2 * stride), nullptr);
+  return poly_apply_impl<float>(c, P, A, (const float*)x, (float*)y, (float*)base,
+                                (float*)(base + stride), (float*)(base + 2 * stride), nullptr);
+}
+
+void poly_prec_destroy(gmr_poly* P) { delete P; }
+
+gmr_status poly_prec_hessenberg(const gmr_poly* P, double* H) {
+  if (!P || !H) return fail(GMR_ERR_INVALID, "poly_prec_hessenberg: null pointer");
+  const int s = (int)P->re.size();
+  for (int j = 0; j < s; ++j)
+    for (int i = 0; i <= s; ++i)
+      H[(size_t)j * (s + 1) + i] = (i > j + 1) ? 0.0 : P->hess[(size_t)j * P->ldh + i];
+  return GMR_OK;
+}
+
+int32_t poly_prec_degree(const gmr_poly* P) { return P ? (int32_t)P->re.size() - 1 : -1; }
+
+gmr_status poly_prec_roots(const gmr_poly* P, double* re, double* im) {
+  if (!P || !re || !im) return fail(GMR_ERR_INVALID, "poly_prec_roots: null pointer");
+  std::copy(P->re.begin(), P->re.end(), re);
+  std::copy(P->im.begin(), P->im.end(), im);
+  return GMR_OK;
+}
+
+static gmr_status solve_common_checks(const gmr_params* params, const void* b, void* x, gmr_result* result) {
+  GMR_TRY(check_params(params));
+  if (!b || !x || !result) return fail(GMR_ERR_INVALID, "null b, x or result");
+  if (b == x) return fail(GMR_ERR_INVALID, "b and x must not overlap");
+  return GMR_OK;
+}
+
+gmr_status gmres_solve(const gmr_csr* A, const gmr_poly* P, const void* b, void* x,
+                       const gmr_params* params, void* ws, size_t ws_bytes, gmr_result* result,
+                       double* hist, void* stream) {
+  GMR_TRY(check_csr(A, "gmres_solve"));
+  GMR_TRY(solve_common_checks(params, b, x, result));
+  if (P && P->dtype != A->dtype) return fail(GMR_ERR_INVALID, "gmres_solve: polynomial dtype differs from A");
+  SolveArgs a{A, A, P, b, x, params, ws, ws_bytes, result, hist, (hipStream_t)stream};
+  if (A->dtype == GMR_F64) return solve_impl<double, double>(a);
+  return solve_impl<float, float>(a);
+}
+
+gmr_status gmres_ir_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly* P,
+                          const double* b, double* x, const gmr_params* params, void* ws,
+                          size_t ws_bytes, gmr_result* result, double* hist, void* stream) {
+  GMR_TRY(check_csr(A64, "gmres_ir_solve(A64)"));
+  GMR_TRY(check_csr(A32, "gmres_ir_solve(A32)"));
+  if (A64->dtype != GMR_F64 || A32->dtype != GMR_F32)
+    return fail(GMR_ERR_INVALID, "gmres_ir_solve: A64 must be float64 and A32 float32");
+  if (A64->n != A32->n || A64->nnz != A32->nnz)
+    return fail(GMR_ERR_INVALID, "gmres_ir_solve: A64 and A32 differ in size");
+  if (P && P->dtype != GMR_F32) return fail(GMR_ERR_INVALID, "gmres_ir_solve: the polynomial must be float32");
+  GMR_TRY(solve_common_checks(params, b, x, result));
+  SolveArgs a{A32, A64, P, b, x, params, ws, ws_bytes, result, hist, (hipStream_t)stream};
+  return solve_impl<float, double>(a);
+}
+
+}  // extern "C"

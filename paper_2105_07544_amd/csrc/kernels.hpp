@@ -1,0 +1,640 @@
+// HIP kernels of the GMRES(m) / GMRES-IR hot path for gfx950.
+//
+//  * CSR SpMV (§V-D) as "CSR-stream": a block owns 256 consecutive rows,
+//    streams their nonzeros with fully coalesced loads, forms the products
+//    val[k] * x[col[k]] into LDS and lets each thread add up its own row in
+//    ascending k.  Epilogues fuse the vector work that follows the product:
+//    the Arnoldi normalisation, the float64 residual b - A x with its norm,
+//    and the GMRES-polynomial recurrences.
+//  * CGS2 (§III-A: two classical Gram-Schmidt passes per iteration) as three
+//    passes over the basis V: dots, update+dots, update+norm.  A wave owns 64
+//    rows (one per lane); the per-column partial dots of those rows are
+//    reduced across lanes by a butterfly, and blocks combine their partials
+//    in float64 in a fixed order (deterministic).
+//  * The least-squares problem of Alg. 1 is solved by Givens rotations in
+//    float64 inside the last block of the update+norm pass.
+#pragma once
+
+#include <math.h>
+
+#include "device_common.hpp"
+
+namespace gmr {
+
+// Rows handled by one SpMV block and nonzeros staged in LDS per pass.
+constexpr int kSpmvRows = 256;
+constexpr int kSpmvChunk = 2048;
+// Upper bound on the number of blocks of a reduction kernel (partials per column).
+constexpr int kMaxRedBlocks = 1024;
+// Basis columns (j) supported by the kernels; H has restart+1 rows.
+constexpr int kMaxCols = 256;
+// Row pitch of the per-block partial array (one slot per column).
+constexpr int kPartPitch = kMaxCols;
+
+// Device-resident state of one GMRES cycle.  Everything the host needs after a
+// cycle sits in `Status`, read back with one small copy.
+struct Status {
+  double gamma;       // ||r|| of the outer residual (float64 or the outer precision)
+  double inv_gamma;   // 1 / gamma
+  double bnorm;       // ||b||
+  double res;         // |g_{k+1}| of the cycle (inner units)
+  double beta0;       // norm of the cast, scaled residual (inner start vector)
+  double stop_thresh; // stop the cycle when |g_{j+1}| <= stop_thresh (< 0: never)
+  int k;              // iterations completed in the cycle
+  int done;           // the cycle ended early (implicit convergence or breakdown)
+  int breakdown;      // h_{j+1,j} was zero (lucky breakdown)
+  int nonfinite;      // NaN/Inf met in the small dense problem
+};
+
+struct CycleState {
+  double* H;        // (ldh x m) rotated Hessenberg -> R, column-major
+  double* Hraw;     // (ldh x m) Hessenberg as built (for the polynomial setup)
+  double* cs;       // m cosines
+  double* sn;       // m sines
+  double* g;        // ldh entries, gamma e1 rotated
+  double* y;        // m entries, least-squares solution (float64)
+  double* h1d;      // kMaxCols, first-pass coefficients (float64 sums)
+  double* h2d;      // kMaxCols, second-pass coefficients
+  double* inv_beta; // 1 / h_{j+1,j} of the latest column (normalisation factor)
+  Status* st;
+  int ldh;          // m + 1
+};
+
+// ===========================================================================
+// SpMV core
+// ===========================================================================
+// Computes, for thread t of the block, the dot product of row (r0 + t) with x
+// (x scaled by `s` when SCALED).  Returns 0 for threads past the last row.
+template <class T, bool SCALED>
+__device__ __forceinline__ T spmv_row(int n, int r0, const int* __restrict__ rp,
+                                      const int* __restrict__ ci, const T* __restrict__ val,
+                                      const T* __restrict__ x, T s, T* s_prod, int* s_rp) {
+  const int t = threadIdx.x;
+  const int nr = min(kSpmvRows, n - r0);
+  for (int i = t; i <= nr; i += kBlock) s_rp[i] = rp[r0 + i];
+  __syncthreads();
+  const int k0 = s_rp[0];
+  const int k1 = s_rp[nr];
+  const int rs = (t < nr) ? s_rp[t] : 0;
+  const int re = (t < nr) ? s_rp[t + 1] : 0;
+  T acc = T(0);
+  for (int c0 = k0; c0 < k1; c0 += kSpmvChunk) {
+    const int c1 = min(c0 + kSpmvChunk, k1);
+    for (int k = c0 + t; k < c1; k += kBlock) {
+      T xv = x[ci[k]];
+      if constexpr (SCALED) xv = xv * s;
+      s_prod[k - c0] = val[k] * xv;
+    }
+    __syncthreads();
+    const int a = max(rs, c0);
+    const int b = min(re, c1);
+    for (int k = a; k < b; ++k) acc += s_prod[k - c0];
+    __syncthreads();
+  }
+  return acc;
+}
+
+// y = A x.  When `scale` is non-null the input is x * (*scale) and, when `vout`
+// is non-null, that scaled input is also written to vout for the block's rows
+// (this is how v_{j+1} = w / h_{j+1,j} is stored without a separate pass).
+template <class T>
+__global__ __launch_bounds__(kBlock) void spmv_kernel(int n, const int* __restrict__ rp,
+                                                      const int* __restrict__ ci,
+                                                      const T* __restrict__ val,
+                                                      const T* __restrict__ x,
+                                                      const double* __restrict__ scale,
+                                                      T* __restrict__ vout, T* __restrict__ y,
+                                                      const int* __restrict__ done) {
+  __shared__ T s_prod[kSpmvChunk];
+  __shared__ int s_rp[kSpmvRows + 1];
+  if (done && *done) return;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
+  const int r = r0 + threadIdx.x;
+  T acc;
+  if (scale) {
+    const T s = T(*scale);
+    acc = spmv_row<T, true>(n, r0, rp, ci, val, x, s, s_prod, s_rp);
+    if (r < n && vout) vout[r] = x[r] * s;
+  } else {
+    acc = spmv_row<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, s_rp);
+  }
+  if (r < n) y[r] = acc;
+}
+
+// r = b - A x with the block's partial ||r||^2 (float64) in partial[blockIdx.x];
+// finish_residual_kernel turns the partials into gamma.
+template <class T>
+__global__ __launch_bounds__(kBlock) void residual_kernel(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci,
+                                                          const T* __restrict__ val,
+                                                          const T* __restrict__ x,
+                                                          const T* __restrict__ b,
+                                                          T* __restrict__ r, double* partial) {
+  __shared__ T s_prod[kSpmvChunk];
+  __shared__ int s_rp[kSpmvRows + 1];
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
+  const int row = r0 + threadIdx.x;
+  T acc = spmv_row<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, s_rp);
+  double sq = 0.0;
+  if (row < n) {
+    T rv = b[row] - acc;
+    r[row] = rv;
+    sq = double(rv) * double(rv);
+  }
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+}
+
+// Sum of nparts float64 partials in a fixed order (one block).
+__device__ __forceinline__ double sum_partials(int nparts, const double* __restrict__ partial) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) s += partial[i];
+  return block_sum(s);
+}
+
+__global__ __launch_bounds__(kBlock) void finish_residual_kernel(int nparts, const double* partial,
+                                                                 Status* st) {
+  const double s = sum_partials(nparts, partial);
+  if (threadIdx.x == 0) {
+    const double g = sqrt(s);
+    st->gamma = g;
+    st->inv_gamma = 1.0 / g;
+  }
+}
+
+// ||v||^2 partials of a vector (float64 accumulation).
+template <class T>
+__global__ __launch_bounds__(kBlock) void norm2_kernel(int n, const T* __restrict__ v,
+                                                       double* partial) {
+  double sq = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double a = double(v[i]);
+    sq += a * a;
+  }
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sq;
+}
+
+// *out = sqrt(sum of partials)
+__global__ __launch_bounds__(kBlock) void finish_norm2_kernel(int nparts, const double* partial,
+                                                              double* out) {
+  const double s = sum_partials(nparts, partial);
+  if (threadIdx.x == 0) *out = sqrt(s);
+}
+
+// Start of a cycle: w = cast(r * (1/gamma)) into the inner precision with the
+// block's partial ||w||^2 accumulated in the inner precision.
+template <class TO, class TI>
+__global__ __launch_bounds__(kBlock) void start_cycle_kernel(int n, const TO* __restrict__ r,
+                                                             TI* __restrict__ w, double* partial,
+                                                             const Status* __restrict__ st) {
+  const TO ig = TO(st->inv_gamma);
+  TI sq = TI(0);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const TI v = TI(r[i] * ig);
+    w[i] = v;
+    sq += v * v;
+  }
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) partial[blockIdx.x] = double(sq);
+}
+
+// beta0 = ||w|| (rounded to the inner precision), g = beta0 e1, cycle flags reset.
+// `stop_rel` >= 0 arms the implicit residual test |g_{j+1}| * gamma <= stop_rel.
+template <class TI>
+__global__ __launch_bounds__(kBlock) void finish_start_cycle_kernel(int nparts, const double* partial,
+                                                                    CycleState cs, double stop_rel) {
+  const double s = sum_partials(nparts, partial);
+  if (threadIdx.x == 0) {
+    const double b0 = sqrt(double(TI(s)));
+    Status* st = cs.st;
+    st->beta0 = b0;
+    cs.g[0] = b0;
+    *cs.inv_beta = 1.0 / b0;
+    st->k = 0;
+    st->done = 0;
+    st->breakdown = 0;
+    st->nonfinite = !(b0 > 0.0) || !isfinite(b0);
+    st->res = b0;
+    st->stop_thresh = (stop_rel >= 0.0) ? stop_rel * st->inv_gamma : -1.0;
+  }
+}
+
+// ===========================================================================
+// CGS2 passes.  All three share the row mapping: wave `gw` of the grid walks
+// row groups grp = gw, gw + G, ... of 64 rows; lane l owns row 64*grp + l.
+// ===========================================================================
+
+// Writes the block's per-column partial sums (held per lane after the
+// butterfly, column = col_of(lane, i), duplicated lanes skipped) into
+// partial[blockIdx.x * kPartPitch + col] as float64, combining the waves of
+// the block in a fixed order.
+template <int K, class T, int NACC>
+__device__ __forceinline__ void publish_col_partials(const T (&acc)[NACC][Butterfly<K>::KOut],
+                                                     int j, double* partial) {
+  constexpr int KO = Butterfly<K>::KOut;
+  __shared__ double s_cols[kWavesPerBlock][kMaxCols];
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  if (Butterfly<K>::owner(lane)) {
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+#pragma unroll
+      for (int i = 0; i < KO; ++i) {
+        const int col = q * K + Butterfly<K>::col_of(lane, i);
+        if (col < j) s_cols[wave][col] = double(acc[q][i]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < j; c += kBlock) {
+    double s = s_cols[0][c];
+#pragma unroll
+    for (int w = 1; w < kWavesPerBlock; ++w) s += s_cols[w][c];
+    partial[(size_t)blockIdx.x * kPartPitch + c] = s;
+  }
+}
+
+// out[c] = sum over the nparts blocks of partial[b][c] (one block per column,
+// fixed order), plus the copy rounded to the working precision.
+template <class T>
+__global__ __launch_bounds__(kBlock) void finish_cols_kernel(int nparts, const double* __restrict__ partial,
+                                                             double* out, T* outT,
+                                                             const int* __restrict__ done) {
+  if (done && *done) return;
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kBlock) s += partial[(size_t)b * kPartPitch + c];
+  s = block_sum(s);
+  if (threadIdx.x == 0) {
+    out[c] = s;
+    outT[c] = T(s);
+  }
+}
+
+// Pass 1: h = V_j^T w  (j <= NQ * K columns, in NQ chunks of K columns).
+template <class T, int K, int NQ>
+__global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T* __restrict__ V,
+                                                          int64_t ldv, const T* __restrict__ w,
+                                                          double* partial,
+                                                          const int* __restrict__ done) {
+  constexpr int KO = Butterfly<K>::KOut;
+  if (done && *done) return;
+  const int lane = threadIdx.x % kWave;
+  const int gw = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const int G = gridDim.x * kWavesPerBlock;
+  const int ngrp = (n + kWave - 1) / kWave;
+  T acc[NQ][KO];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int i = 0; i < KO; ++i) acc[q][i] = T(0);
+  for (int grp = gw; grp < ngrp; grp += G) {
+    const int r = grp * kWave + lane;
+    const bool ok = r < n;
+    const T wv = ok ? w[r] : T(0);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q * K < j) {
+        T a[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          const int col = q * K + c;
+          a[c] = (col < j && ok) ? V[(size_t)col * ldv + r] : T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) a[c] *= wv;
+        Butterfly<K>::run(a, lane);
+#pragma unroll
+        for (int i = 0; i < KO; ++i) acc[q][i] += a[i];
+      }
+    }
+  }
+  publish_col_partials<K, T, NQ>(acc, j, partial);
+}
+
+// Pass-1 update fused with pass-2 dots: w -= V_j h_in ; h_out = V_j^T w.
+// The j basis entries of a row stay in registers between the two uses, so V
+// is read once.  Needs j <= K.
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void cgs_update_dots_kernel(
+    int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
+    T* __restrict__ w, double* partial, const int* __restrict__ done) {
+  constexpr int KO = Butterfly<K>::KOut;
+  __shared__ T s_h[K];
+  if (done && *done) return;
+  for (int c = threadIdx.x; c < K; c += kBlock) s_h[c] = (c < j) ? h_in[c] : T(0);
+  __syncthreads();
+  const int lane = threadIdx.x % kWave;
+  const int gw = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const int G = gridDim.x * kWavesPerBlock;
+  const int ngrp = (n + kWave - 1) / kWave;
+  T acc[1][KO];
+#pragma unroll
+  for (int i = 0; i < KO; ++i) acc[0][i] = T(0);
+  for (int grp = gw; grp < ngrp; grp += G) {
+    const int r = grp * kWave + lane;
+    const bool ok = r < n;
+    T v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] = (c < j && ok) ? V[(size_t)c * ldv + r] : T(0);
+    T wv = ok ? w[r] : T(0);
+#pragma unroll
+    for (int c = 0; c < K; ++c) wv -= v[c] * s_h[c];
+    if (ok) w[r] = wv;
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] *= wv;
+    Butterfly<K>::run(v, lane);
+#pragma unroll
+    for (int i = 0; i < KO; ++i) acc[0][i] += v[i];
+  }
+  publish_col_partials<K, T, 1>(acc, j, partial);
+}
+
+// Plain update w -= V_j h_in (used when j is too large to fuse).
+template <class T>
+__global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const T* __restrict__ V,
+                                                            int64_t ldv, const T* __restrict__ h_in,
+                                                            T* __restrict__ w,
+                                                            const int* __restrict__ done) {
+  __shared__ T s_h[kMaxCols];
+  if (done && *done) return;
+  for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
+  __syncthreads();
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+    T wv = w[r];
+    int c = 0;
+    for (; c + 8 <= j; c += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(c + u) * ldv + r];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wv -= v[u] * s_h[c + u];
+    }
+    for (; c < j; ++c) wv -= V[(size_t)c * ldv + r] * s_h[c];
+    w[r] = wv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tail of the update+norm pass, run by the last block after beta is known.
+// ---------------------------------------------------------------------------
+enum TailMode { kTailGivens = 0, kTailStandalone = 1 };
+
+// Givens step on column jc (0-based) and, when the cycle ends, the triangular
+// solve R y = g.  Thread 0 does the sequential rotation work; the
+// back-substitution is column-oriented across the block.
+__device__ __forceinline__ void givens_tail(CycleState cs, int jc, int last_jc, double beta,
+                                            double breakdown_thresh) {
+  __shared__ int s_finish;
+  __shared__ double s_g[kMaxCols + 1];
+  __shared__ double s_y;
+  const int ldh = cs.ldh;
+  if (threadIdx.x == 0) {
+    double* hcol = cs.H + (size_t)jc * ldh;
+    double* hraw = cs.Hraw + (size_t)jc * ldh;
+    for (int i = 0; i <= jc; ++i) {
+      const double v = cs.h1d[i] + cs.h2d[i];
+      hcol[i] = v;
+      hraw[i] = v;
+    }
+    hcol[jc + 1] = beta;
+    hraw[jc + 1] = beta;
+    for (int i = jc + 2; i < ldh; ++i) {  // below the subdiagonal: exact zeros
+      hcol[i] = 0.0;
+      hraw[i] = 0.0;
+    }
+    for (int i = 0; i < jc; ++i) {
+      const double hi = hcol[i], hi1 = hcol[i + 1];
+      const double c = cs.cs[i], s = cs.sn[i];
+      hcol[i] = c * hi + s * hi1;
+      hcol[i + 1] = -s * hi + c * hi1;
+    }
+    const double a = hcol[jc], b = hcol[jc + 1];
+    const double rho = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (rho != 0.0) {
+      c = a / rho;
+      s = b / rho;
+    }
+    cs.cs[jc] = c;
+    cs.sn[jc] = s;
+    hcol[jc] = c * a + s * b;
+    hcol[jc + 1] = 0.0;
+    const double gj = cs.g[jc];
+    cs.g[jc + 1] = -s * gj;
+    cs.g[jc] = c * gj;
+    const double res = fabs(cs.g[jc + 1]);
+    Status* st = cs.st;
+    st->res = res;
+    const bool brk = !(beta > breakdown_thresh);
+    const bool nonfin = !isfinite(res) || !isfinite(beta) || !isfinite(hcol[jc]);
+    const bool conv = st->stop_thresh >= 0.0 && res <= st->stop_thresh;
+    if (brk) st->breakdown = 1;
+    if (nonfin) st->nonfinite = 1;
+    const bool finish = brk || nonfin || conv || jc == last_jc;
+    if (finish) {
+      st->k = jc + 1;
+      if (brk || conv || nonfin) st->done = 1;
+    }
+    *cs.inv_beta = 1.0 / beta;
+    s_finish = finish ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_finish) return;
+  const int k = jc + 1;
+  for (int i = threadIdx.x; i < k; i += kBlock) s_g[i] = cs.g[i];
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    if (threadIdx.x == 0) {
+      const double yi = s_g[i] / cs.H[(size_t)i * ldh + i];
+      cs.y[i] = yi;
+      s_y = yi;
+    }
+    __syncthreads();
+    const double yi = s_y;
+    for (int t = threadIdx.x; t < i; t += kBlock) s_g[t] -= cs.H[(size_t)i * ldh + t] * yi;
+    __syncthreads();
+  }
+}
+
+// Pass-2 update and norm: w -= V_j h_in with the block's partial ||w||^2
+// accumulated in the working precision.
+template <class T>
+__global__ __launch_bounds__(kBlock) void cgs_update_norm_kernel(
+    int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
+    T* __restrict__ w, double* partial, const int* __restrict__ done) {
+  __shared__ T s_h[kMaxCols];
+  if (done && *done) return;
+  for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
+  __syncthreads();
+  T sq = T(0);
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+    T wv = w[r];
+    int c = 0;
+    for (; c + 16 <= j; c += 16) {
+      T v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = V[(size_t)(c + u) * ldv + r];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) wv -= v[u] * s_h[c + u];
+    }
+    for (; c < j; ++c) wv -= V[(size_t)c * ldv + r] * s_h[c];
+    w[r] = wv;
+    sq += wv * wv;
+  }
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) partial[blockIdx.x] = double(sq);
+}
+
+// beta = ||w|| from the partials, then the tail: the Givens step (solver) or
+// h = h1 + h2, beta (standalone CGS2).
+template <class T, int MODE>
+__global__ __launch_bounds__(kBlock) void finish_norm_kernel(int nparts, const double* partial,
+                                                             CycleState cs, int j, int last_jc,
+                                                             double breakdown_thresh, double* hout,
+                                                             const int* __restrict__ done) {
+  if (done && *done) return;
+  const double s = sum_partials(nparts, partial);
+  // beta in the working precision, as the float32 inner solver would have it
+  const double beta = double(T(sqrt(double(T(s)))));
+  if constexpr (MODE == kTailGivens) {
+    givens_tail(cs, j - 1, last_jc, beta, breakdown_thresh);
+  } else {
+    if (threadIdx.x == 0) *cs.inv_beta = (beta > 0.0) ? 1.0 / beta : 1.0;
+    for (int c = threadIdx.x; c < j; c += kBlock) hout[c] = cs.h1d[c] + cs.h2d[c];
+    if (threadIdx.x == 0) hout[j] = beta;
+  }
+}
+
+// ===========================================================================
+// Element-wise kernels
+// ===========================================================================
+template <class T>
+__global__ __launch_bounds__(kBlock) void scale_kernel(int n, const T* __restrict__ x,
+                                                       const double* __restrict__ scale,
+                                                       T* __restrict__ y,
+                                                       const int* __restrict__ done) {
+  if (done && *done) return;
+  const T s = T(*scale);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = x[i] * s;
+}
+
+// u = V[:, 0:k] y in the working precision (k read from the status), then,
+// when x is given, x += gamma * (TO) u; otherwise u is stored.
+template <class TI, class TO>
+__global__ __launch_bounds__(kBlock) void solution_update_kernel(
+    int n, const TI* __restrict__ V, int64_t ldv, const double* __restrict__ y,
+    const Status* __restrict__ st, TI* __restrict__ u, TO* __restrict__ x) {
+  __shared__ TI s_y[kMaxCols];
+  const int k = st->k;
+  for (int c = threadIdx.x; c < k; c += kBlock) s_y[c] = TI(y[c]);
+  __syncthreads();
+  const TO gam = TO(st->gamma);
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+    TI s = TI(0);
+    for (int c = 0; c < k; ++c) s += V[(size_t)c * ldv + r] * s_y[c];
+    if (x) x[r] += gam * TO(s);
+    else u[r] = s;
+  }
+}
+
+// x += gamma * (TO) u
+template <class TI, class TO>
+__global__ __launch_bounds__(kBlock) void axpy_gamma_kernel(int n, const TI* __restrict__ u,
+                                                            const Status* __restrict__ st,
+                                                            TO* __restrict__ x) {
+  const TO gam = TO(st->gamma);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    x[i] += gam * TO(u[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void cast_f64_f32_kernel(int64_t n, const double* __restrict__ in,
+                                                              float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    out[i] = float(in[i]);
+}
+
+// ===========================================================================
+// GMRES polynomial p(A) = (1 - pi(A)) A^{-1}, pi(z) = prod (1 - z/theta_i),
+// applied from its Leja-ordered roots (§III-D).  With P the running product
+// pi_{i-1}(A) x and Y the running p_{i-1}(A) x:
+//   real root, c = 1/theta:          Y += c P ;  P <- P - c A P
+//   pair a +- ib, c1 = 2a/|theta|^2, c2 = 1/|theta|^2:
+//        T = A P ;  Y += c1 P - c2 T ;  P <- P - (c1 T - c2 A T)
+// Each kernel below is one SpMV with the matching update as its epilogue.
+// ===========================================================================
+
+// Real root: Y (+)= c P ; P_next = P - c (A P)  (first: Y is not read).
+template <class T, bool FIRST>
+__global__ __launch_bounds__(kBlock) void poly_real_kernel(int n, const int* __restrict__ rp,
+                                                           const int* __restrict__ ci,
+                                                           const T* __restrict__ val,
+                                                           const T* __restrict__ P, T c,
+                                                           T* __restrict__ Y, T* __restrict__ Pn,
+                                                           const int* __restrict__ done) {
+  __shared__ T s_prod[kSpmvChunk];
+  __shared__ int s_rp[kSpmvRows + 1];
+  if (done && *done) return;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
+  const int r = r0 + threadIdx.x;
+  const T ap = spmv_row<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, s_rp);
+  if (r < n) {
+    const T p = P[r];
+    Y[r] = FIRST ? c * p : Y[r] + c * p;
+    Pn[r] = p - c * ap;
+  }
+}
+
+// Last real root (no product with A): Y (+)= c P.
+template <class T, bool FIRST>
+__global__ __launch_bounds__(kBlock) void poly_real_last_kernel(int n, const T* __restrict__ P,
+                                                                T c, T* __restrict__ Y,
+                                                                const int* __restrict__ done) {
+  if (done && *done) return;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    Y[i] = FIRST ? c * P[i] : Y[i] + c * P[i];
+}
+
+// Pair, first half: Tt = A P ; Y (+)= c1 P - c2 Tt.
+template <class T, bool FIRST>
+__global__ __launch_bounds__(kBlock) void poly_pair1_kernel(int n, const int* __restrict__ rp,
+                                                            const int* __restrict__ ci,
+                                                            const T* __restrict__ val,
+                                                            const T* __restrict__ P, T c1, T c2,
+                                                            T* __restrict__ Y, T* __restrict__ Tt,
+                                                            const int* __restrict__ done) {
+  __shared__ T s_prod[kSpmvChunk];
+  __shared__ int s_rp[kSpmvRows + 1];
+  if (done && *done) return;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
+  const int r = r0 + threadIdx.x;
+  const T t = spmv_row<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, s_rp);
+  if (r < n) {
+    const T p = P[r];
+    Tt[r] = t;
+    const T inc = c1 * p - c2 * t;
+    Y[r] = FIRST ? inc : Y[r] + inc;
+  }
+}
+
+// Pair, second half: P_next = P - (c1 Tt - c2 A Tt).
+template <class T>
+__global__ __launch_bounds__(kBlock) void poly_pair2_kernel(int n, const int* __restrict__ rp,
+                                                            const int* __restrict__ ci,
+                                                            const T* __restrict__ val,
+                                                            const T* __restrict__ P,
+                                                            const T* __restrict__ Tt, T c1, T c2,
+                                                            T* __restrict__ Pn,
+                                                            const int* __restrict__ done) {
+  __shared__ T s_prod[kSpmvChunk];
+  __shared__ int s_rp[kSpmvRows + 1];
+  if (done && *done) return;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
+  const int r = r0 + threadIdx.x;
+  const T at = spmv_row<T, false>(n, r0, rp, ci, val, Tt, T(1), s_prod, s_rp);
+  if (r < n) Pn[r] = P[r] - (c1 * Tt[r] - c2 * at);
+}
+
+}  // namespace gmr

@@ -1,0 +1,104 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, its
+host routines agree with numpy and the oracle, and bad arguments are
+rejected before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2105_07544_amd as G
+from paper_2105_07544_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "gmres_ir.h")).read()
+    declared = set(re.findall(r"^\s*(?:gmr_status|size_t|void|int32_t|const char\*)\s+(\w+)\s*\(", header, re.M))
+    assert declared == set(_capi.EXPORTED), declared ^ set(_capi.EXPORTED)
+    lib = G.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_hessenberg_eigvals_match_numpy():
+    rng = np.random.default_rng(0)
+    for k in (1, 2, 3, 4, 7, 16, 26, 41, 65):
+        H = np.triu(rng.standard_normal((k, k)), -1)
+        ev = G.hessenberg_eigvals(H)
+        ref = np.linalg.eigvals(H)
+        assert np.allclose(np.sort_complex(ev), np.sort_complex(ref), rtol=1e-10, atol=1e-12)
+    # repeated and clustered eigenvalues of a symmetric tridiagonal
+    T = np.diag(np.full(30, 2.0)) + np.diag(np.full(29, -1.0), 1) + np.diag(np.full(29, -1.0), -1)
+    assert np.allclose(np.sort(G.hessenberg_eigvals(T).real), np.sort(np.linalg.eigvalsh(T)), atol=1e-12)
+
+
+def test_leja_order_matches_oracle():
+    rng = np.random.default_rng(1)
+    for _ in range(40):
+        k = int(rng.integers(1, 45))
+        z = np.linalg.eigvals(np.triu(rng.standard_normal((k, k)), -1))
+        assert np.allclose(G.leja_order(z), O.leja_order(z))
+
+
+def test_workspace_query():
+    a = G.workspace_bytes(1000, 50, G.GMR_F32)
+    b = G.workspace_bytes(1000, 50, G.GMR_F64)
+    c = G.workspace_bytes(1000, 100, G.GMR_F32)
+    d = G.workspace_bytes(1000, 50, G.GMR_F32, True)
+    assert 0 < a < b and a < c and a < d
+    p = _capi.gmr_params(300, 1e-10, 10, 0, 0, 0, 0)
+    assert G.lib().gmres_workspace_bytes(1000, C.byref(p), 0, 0) == 0
+
+
+def test_argument_errors_before_device_work():
+    lib = G.lib()
+    res = _capi.gmr_result()
+    p = _capi.gmr_params(50, 1e-10, 100, 0, 0, 0, 0)
+    # null matrix
+    assert lib.gmres_solve(None, None, None, None, C.byref(p), None, 0, C.byref(res), None, None) == -1
+    assert b"null matrix" in lib.gmr_last_error()
+    A = _capi.gmr_csr(10, 28, 1, 1, 1, 1)
+    bad = _capi.gmr_params(0, 1e-10, 100, 0, 0, 0, 0)
+    assert lib.gmres_solve(C.byref(A), None, 8, 16, C.byref(bad), None, 0, C.byref(res), None, None) == -1
+    bad = _capi.gmr_params(50, -1.0, 100, 0, 0, 0, 0)
+    assert lib.gmres_solve(C.byref(A), None, 8, 16, C.byref(bad), None, 0, C.byref(res), None, None) == -1
+    bad = _capi.gmr_params(257, 1e-10, 100, 0, 0, 0, 0)
+    assert lib.gmres_solve(C.byref(A), None, 8, 16, C.byref(bad), None, 0, C.byref(res), None, None) == -5
+    # dtype mismatch for GMRES-IR
+    assert lib.gmres_ir_solve(C.byref(A), C.byref(A), None, 8, 16, C.byref(p), None, 0, C.byref(res),
+                              None, None) == -1
+    # workspace too small is found before any launch: gmres_solve checks it first
+    with pytest.raises(G.GmresError):
+        _capi.check(lib.cgs2_orth(0, 10, 0, 1, 10, 1, 1, None, 0, None))
+    assert lib.cgs2_orth(0, 10, 300, 1, 10, 1, 1, None, 0, None) == -5
+    assert lib.cgs2_orth(0, 10, 3, 1, 5, 1, 1, None, 0, None) == -1
+    assert lib.cgs2_orth(0, 10, 3, 1, 10, 1, 1, None, 0, None) == -3
+    assert lib.poly_prec_setup(C.byref(A), 80, 1, None, 0, C.byref(C.c_void_p()), None) == -5
+    assert lib.spmv(C.byref(A), 5, 5, None) == -1
+
+
+def test_harmonic_ritz_matches_oracle():
+    import workloads as W
+    for A, d in ((W.convdiff2d(30, 0.05, W.configs.uniflow_wind), 10), (W.laplace2d(12), 7)):
+        v0 = W.poly_start_vector(A.n, 3)
+        _, H, _ = O.arnoldi(A, v0, d + 1)
+        got = np.sort_complex(G.harmonic_ritz(H))
+        ref = np.sort_complex(O.harmonic_ritz_values(H, d + 1))
+        assert np.allclose(got, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_harmonic_ritz_ignores_entries_below_subdiagonal():
+    # only the Hessenberg part of the input may be read
+    import workloads as W
+    A = W.convdiff2d(20, 0.05, W.configs.uniflow_wind)
+    _, H, _ = O.arnoldi(A, W.poly_start_vector(A.n, 1), 9)
+    junk = H.copy()
+    rows, cols = np.tril_indices(10, -2, 9)
+    junk[rows, cols] = np.random.default_rng(0).standard_normal(rows.size) * 1e3
+    assert np.allclose(np.sort_complex(G.harmonic_ritz(junk)), np.sort_complex(G.harmonic_ritz(H)))
+    assert np.allclose(np.sort_complex(G.hessenberg_eigvals(junk[:9, :9])),
+                       np.sort_complex(G.hessenberg_eigvals(H[:9, :9])))

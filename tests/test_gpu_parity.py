@@ -1,0 +1,387 @@
+"""GPU parity: the HIP path through the C ABI against the oracle (MI355X)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+G = pytest.importorskip("paper_2105_07544_amd")
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(A):
+    return G.DeviceCSR.from_host(A, DEV)
+
+
+def t64(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def t32(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def random_csr(n, seed, max_row=9, empty_every=0, long_row=None):
+    rng = np.random.default_rng(seed)
+    rows = []
+    for r in range(n):
+        if empty_every and r % empty_every == 3:
+            rows.append(np.array([], dtype=np.int64))
+            continue
+        k = int(rng.integers(1, max_row + 1))
+        if long_row is not None and r == long_row[0]:
+            k = min(long_row[1], n)
+        rows.append(np.sort(rng.choice(n, size=min(k, n), replace=False)))
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    row_ptr[1:] = np.cumsum([len(c) for c in rows])
+    col = np.concatenate(rows).astype(np.int32) if row_ptr[-1] else np.zeros(0, np.int32)
+    val = rng.standard_normal(len(col))
+    return W.CSR(n, row_ptr, col, val)
+
+
+# ---------------------------------------------------------------------------
+# SpMV: products rounded then summed in ascending k, exactly like the oracle
+# ---------------------------------------------------------------------------
+SPMV_CASES = {
+    "laplace3d_N20": lambda: W.laplace3d(20),
+    "convdiff_N37": lambda: W.convdiff2d(37, 1e-2, W.configs.uniflow_wind),
+    "random_empty_rows": lambda: random_csr(1000, 3, empty_every=7),
+    "random_long_row": lambda: random_csr(5000, 4, long_row=(300, 4500)),
+    "one_row": lambda: W.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.5])),
+    "n_257": lambda: random_csr(257, 5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SPMV_CASES))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_spmv_bit_exact(name, prec):
+    say("spmv", name, prec)
+    A = SPMV_CASES[name]()
+    x = W.uniform_pm1(11, A.n)
+    dt = np.float64 if prec == "f64" else np.float32
+    Ad = dev(A) if prec == "f64" else dev(A).to_f32()
+    xd = t64(x) if prec == "f64" else t32(x)
+    y = host(G.spmv(Ad, xd))
+    ref = O.spmv(A, x.astype(dt), dt)
+    assert np.array_equal(y, ref), np.abs(y - ref).max()
+
+
+def test_spmv_full_config2_sampled():
+    say("spmv full laplace3d N=150")
+    A = W.laplace3d(150)
+    x = W.uniform_pm1(2, A.n)
+    Ad = dev(A)
+    A32 = Ad.to_f32()
+    y64 = host(G.spmv(Ad, t64(x)))
+    y32 = host(G.spmv(A32, t32(x)))
+    rows = np.unique(np.concatenate([np.arange(0, 300), W.uniform_int(9, 0, A.n - 1, 2000),
+                                     np.arange(A.n - 300, A.n)]))
+    for dt, y in ((np.float64, y64), (np.float32, y32)):
+        xs = x.astype(dt)
+        vals = A.val.astype(dt)
+        for r in rows:
+            acc = dt(0)
+            for k in range(A.row_ptr[r], A.row_ptr[r + 1]):
+                acc = dt(acc + vals[k] * xs[A.col_idx[k]])
+            assert y[r] == acc, (dt, r)
+
+
+# ---------------------------------------------------------------------------
+# CGS2
+# ---------------------------------------------------------------------------
+def _basis(n, k, seed, dt):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, k)))
+    return Q.astype(dt)
+
+
+@pytest.mark.parametrize("k", [1, 5, 8, 9, 17, 33, 50, 64, 65, 100, 129, 200, 256])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cgs2_orth_matches_oracle(k, prec):
+    n = 3001 + 17 * k
+    say("cgs2", k, prec, n)
+    dt = np.float64 if prec == "f64" else np.float32
+    V = _basis(n, k, k, dt)
+    w = np.random.default_rng(100 + k).standard_normal(n).astype(dt)
+    ldv = n + 64
+    Vd = torch.zeros((k, ldv), dtype=torch.float64 if prec == "f64" else torch.float32, device=DEV)
+    Vd[:, :n] = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    wd = torch.from_numpy(w.copy()).to(DEV)
+    h = host(G.cgs2_orth(Vd, k, wd, ldv=ldv))
+    wout = host(wd)
+    w_ref, h1, h2, beta = O.cgs2(V, k, w.copy())
+    tol = 1e-12 if prec == "f64" else 2e-5
+    href = h1.astype(np.float64) + h2.astype(np.float64)
+    scale = np.linalg.norm(w.astype(np.float64))
+    assert np.allclose(h[:k], href, rtol=0, atol=tol * scale)
+    assert abs(h[k] - float(beta)) <= tol * scale
+    assert np.allclose(wout, (w_ref / beta).astype(dt), atol=tol * 10)
+    orth = np.abs(V.astype(np.float64).T @ wout.astype(np.float64)).max()
+    assert orth < (1e-14 if prec == "f64" else 1e-6)
+
+
+def test_cgs2_twice_is_enough_f32():
+    # a nearly dependent w: one pass would leave O(eps * cond) components
+    n, k = 20000, 30
+    V = _basis(n, k, 7, np.float32)
+    c = np.random.default_rng(8).standard_normal(k).astype(np.float32)
+    w = (V @ c + 1e-4 * np.random.default_rng(9).standard_normal(n)).astype(np.float32)
+    Vd = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
+    wd = torch.from_numpy(w).to(DEV)
+    G.cgs2_orth(Vd, k, wd)
+    wout = host(wd).astype(np.float64)
+    assert np.abs(V.astype(np.float64).T @ wout).max() < 5e-6
+
+
+# ---------------------------------------------------------------------------
+# Solvers
+# ---------------------------------------------------------------------------
+def _cfg1():
+    return W.config1_laplace2d()
+
+
+def test_gmres_f64_config1_against_oracle():
+    say("gmres f64 config1")
+    p = _cfg1()
+    A = dev(p.A)
+    x, res = G.gmres_solve(A, t64(p.b), restart=50, tol=1e-10, max_iters=20000)
+    ref = O.gmres(p.A, p.b, np.zeros(p.A.n), 50, 1e-10, 20000)
+    say(res.iters, res.cycles, res.rel_res, "oracle", ref.iters, ref.cycles, ref.rel_res)
+    assert res.converged and res.rel_res <= 1e-10
+    xh = host(x)
+    true = np.linalg.norm(p.b - O.spmv(p.A, xh)) / np.linalg.norm(p.b)
+    assert true <= 1e-10
+    assert abs(res.iters - ref.iters) <= max(2, 0.02 * ref.iters)
+    assert np.linalg.norm(xh - 1.0) / np.sqrt(p.A.n) <= 1711.7 * 1e-10 * 10
+
+
+def test_gmres_ir_config1_against_oracle():
+    say("gmres-ir config1")
+    p = _cfg1()
+    A = dev(p.A)
+    x, res = G.gmres_ir_solve(A, A.to_f32(), t64(p.b), restart=50, tol=1e-10, max_iters=20000)
+    ref = O.gmres_ir(p.A, p.b, np.zeros(p.A.n), 50, 1e-10, 20000)
+    say(res.iters, res.cycles, res.rel_res, "oracle", ref.iters, ref.cycles, ref.rel_res)
+    assert res.converged and res.rel_res <= 1e-10
+    assert res.iters % 50 == 0
+    assert abs(res.cycles - ref.cycles) <= max(1, 0.1 * ref.cycles)
+    xh = host(x)
+    assert np.linalg.norm(p.b - O.spmv(p.A, xh)) / np.linalg.norm(p.b) <= 1e-10
+    # the per-restart residual history follows the oracle's
+    h, hr = np.array(res.history), np.array(ref.history)
+    k = min(len(h), len(hr))
+    assert np.all(np.abs(np.log10(h[:k]) - np.log10(hr[:k])) < 1.0)
+
+
+def test_gmres_f32_only_stalls():
+    say("gmres f32-only config1")
+    p = _cfg1()
+    A32 = dev(p.A).to_f32()
+    x, res = G.gmres_solve(A32, t32(p.b), restart=50, tol=1e-10, max_iters=2000)
+    assert res.status == 1
+    assert 1e-8 < min(res.history) < 1e-5
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_nonsymmetric_dense_solve(seed):
+    rng = np.random.default_rng(seed)
+    n = 16 + 8 * seed
+    D = np.eye(n) * 3 + rng.standard_normal((n, n)) / np.sqrt(n)
+    rows, cols = np.nonzero(D)
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, rows + 1, 1)
+    A = W.CSR(n, np.cumsum(rp).astype(np.int32), cols.astype(np.int32), D[rows, cols])
+    b = rng.standard_normal(n)
+    xs = np.linalg.solve(D, b)
+    kappa = np.linalg.cond(D)
+    Ad = dev(A)
+    x1, r1 = G.gmres_solve(Ad, t64(b), restart=8, tol=1e-10, max_iters=1000)
+    x2, r2 = G.gmres_ir_solve(Ad, Ad.to_f32(), t64(b), restart=8, tol=1e-10, max_iters=1000)
+    for x, r in ((x1, r1), (x2, r2)):
+        assert r.converged
+        assert np.linalg.norm(host(x) - xs) / np.linalg.norm(xs) <= 10 * kappa * 1e-10
+
+
+def test_determinism_bitwise():
+    p = W.config2_laplace3d(N=24)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    xa, ra = G.gmres_ir_solve(A, A32, t64(p.b), restart=30, tol=1e-10, max_iters=5000)
+    xb, rb = G.gmres_ir_solve(A, A32, t64(p.b), restart=30, tol=1e-10, max_iters=5000)
+    assert np.array_equal(host(xa), host(xb)) and ra.history == rb.history
+
+
+def test_resume_from_returned_x_is_bitwise_equal():
+    p = W.config2_laplace3d(N=20)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    b = t64(p.b)
+    xa, ra = G.gmres_ir_solve(A, A32, b, restart=20, tol=1e-10, max_iters=5000)
+    xb, rb1 = G.gmres_ir_solve(A, A32, b, restart=20, tol=1e-10, max_iters=5000, max_cycles=3)
+    assert rb1.status == 1
+    xb, rb2 = G.gmres_ir_solve(A, A32, b, xb, restart=20, tol=1e-10, max_iters=5000)
+    assert np.array_equal(host(xa), host(xb))
+    assert rb1.cycles + rb2.cycles == ra.cycles
+
+
+def test_error_paths():
+    p = W.config2_laplace3d(N=10)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    b = t64(p.b)
+    small = G.alloc_workspace(1024, DEV)
+    with pytest.raises(G.GmresError) as e:
+        G.gmres_ir_solve(A, A32, b, ws=small)
+    assert e.value.status == -3
+    bn = b.clone()
+    bn[5] = float("nan")
+    with pytest.raises(G.GmresError) as e:
+        G.gmres_ir_solve(A, A32, bn)
+    assert e.value.status == -4
+    x, r = G.gmres_ir_solve(A, A32, b, restart=5, max_iters=10)
+    assert r.status == 1 and r.iters == 10
+    x, r = G.gmres_ir_solve(A, A32, torch.zeros_like(b))
+    assert r.status == 0 and float(host(x).max()) == 0.0
+
+
+def test_ir_self_corrects_a_corrupted_iterate():
+    # a damaged x between restarts is repaired by the float64 residual
+    p = W.config2_laplace3d(N=16)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    b = t64(p.b)
+    x, r1 = G.gmres_ir_solve(A, A32, b, restart=20, max_cycles=2)
+    x[::7] += 1.0
+    x, r2 = G.gmres_ir_solve(A, A32, b, x, restart=20, max_iters=20000)
+    assert r2.converged and r2.rel_res <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# GMRES polynomial
+# ---------------------------------------------------------------------------
+def test_poly_roots_and_apply_f64():
+    say("poly f64")
+    A = W.convdiff2d(30, 0.05, W.configs.uniflow_wind)
+    v0 = W.poly_start_vector(A.n, 3)
+    Ad = dev(A)
+    P = G.poly_prec_setup(Ad, 10, t64(v0))
+    roots = P.roots()
+    ref = O.poly_roots(A, 10, v0, np.float64)
+    assert P.degree == 10
+    Hg = P.hessenberg()
+    _, Hr, _ = O.arnoldi(A, v0, 11)
+    say("max |H_gpu - H_oracle|", np.abs(Hg - Hr).max(), np.abs(Hr).max())
+    assert np.allclose(Hg, Hr, rtol=0, atol=1e-12 * np.abs(Hr).max())
+    assert np.allclose(np.sort_complex(roots), np.sort_complex(ref), rtol=1e-7, atol=1e-10)
+    x = W.uniform_pm1(5, A.n)
+    y = host(G.poly_prec_apply(P, Ad, t64(x)))
+    yref = O.poly_apply(A, ref, x, np.float64)
+    assert np.allclose(y, yref, rtol=1e-8, atol=1e-8 * np.abs(yref).max())
+    # pin (i): ||v - A p(A) v|| equals the (d+1)-step GMRES residual from v
+    v = v0 / np.linalg.norm(v0)
+    pv = host(G.poly_prec_apply(P, Ad, t64(v)))
+    res = np.linalg.norm(v - O.spmv(A, pv))
+    out = O.gmres(A, v, np.zeros(A.n), 11, 1e-300, 11, max_cycles=1)
+    assert np.isclose(res, out.implicit_history[-1] * np.linalg.norm(v), rtol=1e-6)
+
+
+def test_poly_exact_inverse_diagonal():
+    d = np.repeat([0.5, 1.0, 2.0, 4.0, 6.0, 9.0], 50)
+    n = d.size
+    A = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    Ad = dev(A)
+    v = W.uniform01(6, n) + 0.5
+    P = G.poly_prec_setup(Ad, 5, t64(v))
+    y = host(G.poly_prec_apply(P, Ad, t64(v)))
+    assert np.allclose(d * y, v, rtol=1e-9)
+
+
+def test_poly_f32_apply_close_to_oracle():
+    A = W.laplace2d(40)
+    v0 = W.poly_start_vector(A.n, 9)
+    A32 = dev(A).to_f32()
+    P = G.poly_prec_setup(A32, 8, t32(v0))
+    r = P.roots()
+    assert np.all(np.abs(r.imag) == 0) and np.all(r.real > 0)
+    x = W.uniform_pm1(12, A.n)
+    y = host(G.poly_prec_apply(P, A32, t32(x))).astype(np.float64)
+    yref = O.poly_apply(A, r, x, np.float64)
+    assert np.allclose(y, yref, rtol=0, atol=2e-4 * np.abs(yref).max())
+
+
+def test_gmres_ir_poly_small_convdiff():
+    say("gmres-ir + poly convdiff N=60")
+    p = W.config3_convdiff(N=60, restart=20, degree=8)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    v0 = W.poly_start_vector(p.A.n, p.poly_seed)
+    P32 = G.poly_prec_setup(A32, 8, t32(v0))
+    x, res = G.gmres_ir_solve(A, A32, t64(p.b), restart=20, tol=1e-10, max_iters=20000, P=P32)
+    assert res.converged and res.iters % 20 == 0
+    xh = host(x)
+    assert np.linalg.norm(p.b - O.spmv(p.A, xh)) / np.linalg.norm(p.b) <= 1e-10
+    roots32 = P32.roots()
+    prec = lambda v: O.poly_apply(p.A, roots32, v, np.float32)
+    ref = O.gmres_ir(p.A, p.b, np.zeros(p.A.n), 20, 1e-10, 20000, prec32=prec)
+    say(res.cycles, ref.cycles)
+    assert abs(res.cycles - ref.cycles) <= max(1, 0.1 * ref.cycles)
+    # float64 GMRES with a float64 polynomial reaches the tolerance too
+    P64 = G.poly_prec_setup(A, 8, t64(v0))
+    x64, r64 = G.gmres_solve(A, t64(p.b), restart=20, tol=1e-10, max_iters=20000, P=P64)
+    assert r64.converged
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads (properties that hold at any size)
+# ---------------------------------------------------------------------------
+def test_config2_full_gmres_ir_reaches_1e10():
+    say("config2 full gmres-ir")
+    p = W.config2_laplace3d()
+    A = dev(p.A)
+    A32 = A.to_f32()
+    x, res = G.gmres_ir_solve(A, A32, t64(p.b), restart=50, tol=1e-10, max_iters=20000)
+    say(res.iters, res.cycles, res.rel_res, res.seconds)
+    assert res.converged and res.iters % 50 == 0
+    xh = host(x)
+    assert np.linalg.norm(p.b - O.spmv(p.A, xh)) / np.linalg.norm(p.b) <= 1e-10
+    fwd = np.linalg.norm(xh - p.x_true) / np.linalg.norm(p.x_true)
+    assert fwd <= 9240.2 * 1e-10 * 10
+
+
+@pytest.mark.parametrize("fill", [0x00, 0xFF, 0x7F])
+def test_poisoned_workspace_gives_identical_results(fill):
+    # every workspace byte the solver reads it has written first: a workspace
+    # full of NaN (0xFF) or huge values (0x7F) gives the same bits as zeros
+    say("poisoned workspace", fill)
+    p = W.config3_convdiff(N=40, restart=15, degree=6)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    v0 = t32(W.poly_start_vector(p.A.n, p.poly_seed))
+    nb = G.workspace_bytes(p.A.n, 15, G.GMR_F32, True)
+    ws = G.alloc_workspace(nb, DEV)
+    ws.fill_(fill)
+    P32 = G.poly_prec_setup(A32, 6, v0, ws=ws)
+    ws.fill_(fill)
+    x, res = G.gmres_ir_solve(A, A32, t64(p.b), restart=15, max_iters=3000, P=P32, ws=ws)
+    ws0 = G.alloc_workspace(nb, DEV)
+    ws0.zero_()
+    P0 = G.poly_prec_setup(A32, 6, v0, ws=ws0)
+    x0, res0 = G.gmres_ir_solve(A, A32, t64(p.b), restart=15, max_iters=3000, P=P0, ws=ws0)
+    assert np.array_equal(P32.roots(), P0.roots())
+    assert res.converged and np.array_equal(host(x), host(x0))
