@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="replay each restart cycle as a hipGraph (no per-kernel events then)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
@@ -103,38 +105,47 @@ def main():
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
 
+    graph = bool(args.graph)
+
     def ir(prof="none"):
         x.zero_()
-        return G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir, prof=prof)[1]
+        return G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir,
+                                prof=prof, graph=graph)[1]
 
     def f64(prof="none"):
         x.zero_()
-        return G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_64, prof=prof)[1]
+        return G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_64, prof=prof,
+                             graph=graph)[1]
 
     log("bench: warmup")
-    unprof = []
-    for _ in range(args.warmup):
-        r = ir()
-        unprof.append(r.seconds)
-    # timed region: K complete GMRES-IR solves; the dominant kernel's launches
-    # are bracketed by HIP events on the solver's stream
+    unprof = [ir().seconds for _ in range(args.warmup)]
+    # timed region: K complete GMRES-IR solves; every launch of the dominant
+    # kernel is bracketed by HIP events on the solver's stream (graph replay
+    # has no per-kernel events, so the timed solves launch eagerly unless
+    # --graph 1 is given, in which case K more eager solves give the roofline)
     log(f"bench: timing {args.steps} GMRES-IR solves")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = []
     for _ in range(args.steps):
-        res.append(ir(prof=DOMINANT))
+        res.append(ir(prof="none" if graph else DOMINANT))
     torch.cuda.synchronize()
     t_ir = (time.perf_counter() - t0) / args.steps
+    if graph:
+        graph = False
+        pres = [ir(prof=DOMINANT) for _ in range(args.steps)]
+        graph = True
+    else:
+        pres = res
     last = res[-1]
     assert all(r.converged for r in res), [r.status_name for r in res]
     xh = x.cpu().numpy()
     import oracle as O  # the explicit residual check runs in float64 on the host
     rel = float(np.linalg.norm(prob.b - O.spmv(prob.A, xh)) / np.linalg.norm(prob.b))
     fwd = float(np.linalg.norm(xh - prob.x_true) / np.linalg.norm(prob.x_true))
-    prof_ms = sum(r.prof_ms for r in res)
-    prof_bytes = sum(r.prof_bytes for r in res)
-    prof_launches = sum(r.prof_launches for r in res)
+    prof_ms = sum(r.prof_ms for r in pres)
+    prof_bytes = sum(r.prof_bytes for r in pres)
+    prof_launches = sum(r.prof_launches for r in pres)
     achieved = prof_bytes / (prof_ms * 1e-3) / 1e9 if prof_ms > 0 else 0.0
     log(f"bench: IR {t_ir:.3f} s/solve, {last.iters} iters, {last.cycles} cycles")
 
@@ -183,6 +194,7 @@ def main():
         "fp64_iters": r64[-1].iters, "fp64_cycles": r64[-1].cycles,
         "rel_res": rel, "forward_error": fwd,
         "ms_per_step_unprofiled": round(1e3 * float(np.median(unprof)), 3) if unprof else None,
+        "graph": bool(args.graph),
         "roofline": {"kernel": DOMINANT, "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launches": prof_launches,

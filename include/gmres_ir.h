@@ -22,7 +22,8 @@
  *    A positive status from a solver means x holds the best iterate found.
  *  - Index arrays are int32 (row_ptr has n+1 entries, col_idx nnz entries,
  *    columns ascending within a row is not required); values are float32 or
- *    float64 as `dtype` says.
+ *    float64 as `dtype` says.  col_idx and val must be 16-byte aligned (the
+ *    SpMV reads them with 16-byte vector loads); GMR_ERR_INVALID otherwise.
  *  - Dense vectors are contiguous; the Krylov basis V is column-major with
  *    leading dimension ldv >= n.
  */
@@ -74,8 +75,13 @@ typedef struct {
   int32_t stagnation_cycles; /* GMRES-IR: give up after this many restarts without
                                 the residual decreasing by 1 %, 0 = never                  */
   int32_t prof_kernel;       /* gmr_prof_kernel                                            */
-  int32_t reserved;
+  int32_t flags;             /* GMR_FLAG_* bits                                            */
 } gmr_params;
+
+/* gmr_params.flags: capture one restart cycle as a hipGraph and replay it each
+ * restart (ignored while profiling).  The solve then runs on a library-owned
+ * non-blocking stream after `stream` has drained; results are the same bits. */
+#define GMR_FLAG_GRAPH 1
 
 typedef struct {
   int32_t status;            /* gmr_status                                                 */

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmresir.so")
 
 GMR_F32, GMR_F64 = 0, 1
+GMR_FLAG_GRAPH = 1
 STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", -1: "GMR_ERR_INVALID",
           -2: "GMR_ERR_HIP", -3: "GMR_ERR_WORKSPACE", -4: "GMR_ERR_NONFINITE",
           -5: "GMR_ERR_UNSUPPORTED"}
@@ -32,7 +33,7 @@ class gmr_csr(C.Structure):
 class gmr_params(C.Structure):
     _fields_ = [("restart", C.c_int32), ("tol", C.c_double), ("max_iters", C.c_int64),
                 ("max_cycles", C.c_int32), ("stagnation_cycles", C.c_int32),
-                ("prof_kernel", C.c_int32), ("reserved", C.c_int32)]
+                ("prof_kernel", C.c_int32), ("flags", C.c_int32)]
 
 
 class gmr_result(C.Structure):

@@ -66,7 +66,7 @@ static Small small_layout(int n) {
   Small L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
-  const size_t npart = std::max<size_t>((size_t)kMaxRedBlocks * kPartPitch, (size_t)spmv_grid(n));
+  const size_t npart = std::max<size_t>((size_t)kMaxCols * kPartPitch, (size_t)spmv_grid(n));
   L.partial = take(npart * 8);
   const size_t hsz = (size_t)(kMaxCols + 1) * kMaxCols * 8;
   L.H = take(hsz);
@@ -196,6 +196,8 @@ static gmr_status check_csr(const gmr_csr* A, const char* who) {
     return fail(GMR_ERR_INVALID, std::string(who) + ": null CSR array");
   if (A->dtype != GMR_F32 && A->dtype != GMR_F64)
     return fail(GMR_ERR_INVALID, std::string(who) + ": unknown dtype");
+  if (((uintptr_t)A->col_idx | (uintptr_t)A->val) % 16 != 0)
+    return fail(GMR_ERR_INVALID, std::string(who) + ": col_idx and val must be 16-byte aligned");
   return GMR_OK;
 }
 
@@ -415,6 +417,49 @@ static gmr_status check_params(const gmr_params* p) {
   return GMR_OK;
 }
 
+// One restart cycle captured as a hipGraph and replayed every restart.  The
+// kernels' arguments (pointers, column counts) are the same in every cycle;
+// a shorter final cycle (max_iters) is captured again.
+struct CycleGraph {
+  bool use = false;
+  hipGraphExec_t exec = nullptr;
+  int mc = -1;
+  template <class F>
+  gmr_status capture(hipStream_t s, F&& body) {
+    if (exec) {
+      hipGraphExecDestroy(exec);
+      exec = nullptr;
+    }
+    GMR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const gmr_status st = body();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != GMR_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(GMR_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(GMR_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    return GMR_OK;
+  }
+  ~CycleGraph() {
+    if (exec) hipGraphExecDestroy(exec);
+  }
+};
+
+// A non-blocking stream of default priority per device, created on first use.
+static gmr_status library_stream(hipStream_t* out) {
+  static thread_local hipStream_t streams[64] = {};
+  int dev = 0;
+  GMR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(GMR_ERR_UNSUPPORTED, "device index >= 64");
+  if (!streams[dev]) GMR_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  *out = streams[dev];
+  return GMR_OK;
+}
+
 template <class TI, class TO>
 static gmr_status solve_impl(const SolveArgs& a) {
   const auto t_start = std::chrono::steady_clock::now();
@@ -429,6 +474,14 @@ static gmr_status solve_impl(const SolveArgs& a) {
     return fail(GMR_ERR_WORKSPACE, "workspace too small: need " + std::to_string(B.end) + " bytes");
 
   Ctx c{a.stream, nullptr};
+  CycleGraph graph;
+  graph.use = (prm.flags & GMR_FLAG_GRAPH) && prm.prof_kernel == GMR_PROF_NONE;
+  if (graph.use) {
+    // capture needs a stream other than the legacy default one: the solve runs
+    // on the library's own stream once the caller's stream has drained
+    GMR_HIP(hipStreamSynchronize(a.stream));
+    GMR_TRY(library_stream(&c.s));
+  }
   Prof& pf = prof_state();
   pf.family = prm.prof_kernel;
   pf.used = 0;
@@ -486,26 +539,14 @@ static gmr_status solve_impl(const SolveArgs& a) {
   }
   double gamma = st.gamma;
   push_hist(gamma / bnorm);
-  int64_t it = 0;
-  double best = gamma;
-  int since_best = 0;
-  gmr_status final_status = GMR_NOT_CONVERGED;
-  while (true) {
-    const double rel = gamma / bnorm;
-    if (!std::isfinite(rel)) { final_status = GMR_ERR_NONFINITE; fail(GMR_ERR_NONFINITE, "non-finite residual"); break; }
-    if (rel <= prm.tol) { final_status = GMR_OK; break; }
-    if (it >= prm.max_iters || (prm.max_cycles > 0 && R.cycles >= prm.max_cycles)) break;
-    if (prm.stagnation_cycles > 0 && R.cycles > 0) {
-      if (gamma < 0.99 * best) { best = gamma; since_best = 0; }
-      else if (++since_best >= prm.stagnation_cycles) { final_status = GMR_STAGNATED; break; }
-    }
-    // --- one cycle ---
+  // Everything one restart cycle enqueues: the cast of r, mc inner iterations,
+  // the solution update and the next residual (with its norm).
+  auto enqueue_cycle = [&](int mc) -> gmr_status {
     start_cycle_kernel<TO, TI><<<stream_grid(n), kBlock, 0, c.s>>>(n, r, W[0], ws.partial(), st_dev);
     GMR_TRY(check_launch("start_cycle_kernel"));
     finish_start_cycle_kernel<TI><<<1, kBlock, 0, c.s>>>(stream_grid(n), ws.partial(), cs,
                                                          implicit_stop ? prm.tol * bnorm : -1.0);
     GMR_TRY(check_launch("finish_start_cycle_kernel"));
-    const int mc = (int)std::min<int64_t>(m, prm.max_iters - it);
     int cur = 0;
     for (int j = 0; j < mc; ++j) {
       TI* vj = V + (size_t)j * B.ldv;
@@ -535,8 +576,35 @@ static gmr_status solve_impl(const SolveArgs& a) {
       solution_update_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, V, B.ldv, cs.y, st_dev, nullptr, x);
       GMR_TRY(check_launch("solution_update_kernel"));
     }
+    if (graph.use) return residual();
+    return GMR_OK;
+  };
+  int64_t it = 0;
+  double best = gamma;
+  int since_best = 0;
+  gmr_status final_status = GMR_NOT_CONVERGED;
+  while (true) {
+    const double rel = gamma / bnorm;
+    if (!std::isfinite(rel)) { final_status = GMR_ERR_NONFINITE; fail(GMR_ERR_NONFINITE, "non-finite residual"); break; }
+    if (rel <= prm.tol) { final_status = GMR_OK; break; }
+    if (it >= prm.max_iters || (prm.max_cycles > 0 && R.cycles >= prm.max_cycles)) break;
+    if (prm.stagnation_cycles > 0 && R.cycles > 0) {
+      if (gamma < 0.99 * best) { best = gamma; since_best = 0; }
+      else if (++since_best >= prm.stagnation_cycles) { final_status = GMR_STAGNATED; break; }
+    }
+    // --- one cycle ---
+    const int mc = (int)std::min<int64_t>(m, prm.max_iters - it);
+    if (graph.use) {
+      if (!graph.exec || graph.mc != mc) {
+        GMR_TRY(graph.capture(c.s, [&]() { return enqueue_cycle(mc); }));
+        graph.mc = mc;
+      }
+      GMR_HIP(hipGraphLaunch(graph.exec, c.s));
+    } else {
+      GMR_TRY(enqueue_cycle(mc));
+      GMR_TRY(residual());
+    }
     const double gamma_cycle = gamma;
-    GMR_TRY(residual());
     GMR_HIP(hipMemcpyAsync(&st, st_dev, sizeof(Status), hipMemcpyDeviceToHost, c.s));
     GMR_HIP(hipStreamSynchronize(c.s));
     it += st.k;

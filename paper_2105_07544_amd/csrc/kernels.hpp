@@ -28,8 +28,9 @@ constexpr int kSpmvChunk = 2048;
 constexpr int kMaxRedBlocks = 1024;
 // Basis columns (j) supported by the kernels; H has restart+1 rows.
 constexpr int kMaxCols = 256;
-// Row pitch of the per-block partial array (one slot per column).
-constexpr int kPartPitch = kMaxCols;
+// Column partials are stored column-major: partial[c * kPartPitch + block], so
+// the finish kernel of column c reads one contiguous run.
+constexpr int kPartPitch = kMaxRedBlocks;
 
 // Device-resident state of one GMRES cycle.  Everything the host needs after a
 // cycle sits in `Status`, read back with one small copy.
@@ -63,32 +64,82 @@ struct CycleState {
 // ===========================================================================
 // SpMV core
 // ===========================================================================
+// Loads the 4 consecutive CSR entries starting at kk (a multiple of 4) with
+// 16-byte vector loads when they lie inside the arrays (col_idx and val are
+// 16-byte aligned, which the host checks), element by element at the end.
+template <class T>
+__device__ __forceinline__ void load_quad(const int* __restrict__ ci, const T* __restrict__ val,
+                                          int kk, int nnz, int (&c)[4], T (&a)[4]) {
+  if (kk + 4 <= nnz) {
+    const int4 c4 = *reinterpret_cast<const int4*>(ci + kk);
+    c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
+    if constexpr (sizeof(T) == 4) {
+      const float4 a4 = *reinterpret_cast<const float4*>(val + kk);
+      a[0] = a4.x; a[1] = a4.y; a[2] = a4.z; a[3] = a4.w;
+    } else {
+      const double2 a0 = *reinterpret_cast<const double2*>(val + kk);
+      const double2 a1 = *reinterpret_cast<const double2*>(val + kk + 2);
+      a[0] = a0.x; a[1] = a0.y; a[2] = a1.x; a[3] = a1.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = kk + i;
+      c[i] = (k < nnz) ? ci[k] : 0;
+      a[i] = (k < nnz) ? val[k] : T(0);
+    }
+  }
+}
+
 // Computes, for thread t of the block, the dot product of row (r0 + t) with x
 // (x scaled by `s` when SCALED).  Returns 0 for threads past the last row.
+// The block's nonzeros are processed in passes of kSpmvChunk entries that
+// start on a multiple of 4: each thread loads two quads of (col, val) with
+// vector loads, gathers x for the entries that belong to the block, stores the
+// rounded products in LDS, and then adds up its own row in ascending k.
 template <class T, bool SCALED>
 __device__ __forceinline__ T spmv_row(int n, int r0, const int* __restrict__ rp,
                                       const int* __restrict__ ci, const T* __restrict__ val,
                                       const T* __restrict__ x, T s, T* s_prod, int* s_rp) {
+  __shared__ int s_nnz;
   const int t = threadIdx.x;
   const int nr = min(kSpmvRows, n - r0);
   for (int i = t; i <= nr; i += kBlock) s_rp[i] = rp[r0 + i];
+  if (t == 0) s_nnz = rp[n];
   __syncthreads();
   const int k0 = s_rp[0];
   const int k1 = s_rp[nr];
+  const int nnz = s_nnz;
   const int rs = (t < nr) ? s_rp[t] : 0;
   const int re = (t < nr) ? s_rp[t + 1] : 0;
   T acc = T(0);
-  for (int c0 = k0; c0 < k1; c0 += kSpmvChunk) {
-    const int c1 = min(c0 + kSpmvChunk, k1);
-    for (int k = c0 + t; k < c1; k += kBlock) {
-      T xv = x[ci[k]];
-      if constexpr (SCALED) xv = xv * s;
-      s_prod[k - c0] = val[k] * xv;
-    }
+  constexpr int Q = kSpmvChunk / (4 * kBlock);  // quads per thread per pass
+  for (int base = k0 & ~3; base < k1; base += kSpmvChunk) {
+    int col[Q][4];
+    T a[Q][4];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) load_quad<T>(ci, val, base + 4 * (t + q * kBlock), nnz, col[q], a[q]);
+    T xv[Q][4];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = base + 4 * (t + q * kBlock) + i;
+        xv[q][i] = (k >= k0 && k < k1) ? x[col[q][i]] : T(0);
+      }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = base + 4 * (t + q * kBlock) + i;
+        T v = xv[q][i];
+        if constexpr (SCALED) v = v * s;
+        if (k >= k0 && k < k1) s_prod[k - base] = a[q][i] * v;
+      }
     __syncthreads();
-    const int a = max(rs, c0);
-    const int b = min(re, c1);
-    for (int k = a; k < b; ++k) acc += s_prod[k - c0];
+    const int lo = max(rs, base);
+    const int hi = min(re, base + kSpmvChunk);
+    for (int k = lo; k < hi; ++k) acc += s_prod[k - base];
     __syncthreads();
   }
   return acc;
@@ -227,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void finish_start_cycle_kernel(int nparts, 
 
 // Writes the block's per-column partial sums (held per lane after the
 // butterfly, column = col_of(lane, i), duplicated lanes skipped) into
-// partial[blockIdx.x * kPartPitch + col] as float64, combining the waves of
+// partial[col * kPartPitch + blockIdx.x] as float64, combining the waves of
 // the block in a fixed order.
 template <int K, class T, int NACC>
 __device__ __forceinline__ void publish_col_partials(const T (&acc)[NACC][Butterfly<K>::KOut],
@@ -251,7 +302,7 @@ __device__ __forceinline__ void publish_col_partials(const T (&acc)[NACC][Butter
     double s = s_cols[0][c];
 #pragma unroll
     for (int w = 1; w < kWavesPerBlock; ++w) s += s_cols[w][c];
-    partial[(size_t)blockIdx.x * kPartPitch + c] = s;
+    partial[(size_t)c * kPartPitch + blockIdx.x] = s;
   }
 }
 
@@ -264,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void finish_cols_kernel(int nparts, const d
   if (done && *done) return;
   const int c = blockIdx.x;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += kBlock) s += partial[(size_t)b * kPartPitch + c];
+  for (int b = threadIdx.x; b < nparts; b += kBlock) s += partial[(size_t)c * kPartPitch + b];
   s = block_sum(s);
   if (threadIdx.x == 0) {
     out[c] = s;
@@ -382,35 +433,43 @@ __global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const 
 enum TailMode { kTailGivens = 0, kTailStandalone = 1 };
 
 // Givens step on column jc (0-based) and, when the cycle ends, the triangular
-// solve R y = g.  Thread 0 does the sequential rotation work; the
-// back-substitution is column-oriented across the block.
+// solve R y = g.  The block first stages the new column (h1 + h2, beta) and
+// the earlier rotations in LDS with one round of parallel loads; thread 0 then
+// does the sequential rotation work on LDS, and the block writes the raw and
+// rotated columns back.  The back-substitution is column-oriented.
 __device__ __forceinline__ void givens_tail(CycleState cs, int jc, int last_jc, double beta,
                                             double breakdown_thresh) {
   __shared__ int s_finish;
+  __shared__ double s_col[kMaxCols + 1];
+  __shared__ double s_c[kMaxCols];
+  __shared__ double s_s[kMaxCols];
   __shared__ double s_g[kMaxCols + 1];
   __shared__ double s_y;
   const int ldh = cs.ldh;
-  if (threadIdx.x == 0) {
-    double* hcol = cs.H + (size_t)jc * ldh;
-    double* hraw = cs.Hraw + (size_t)jc * ldh;
-    for (int i = 0; i <= jc; ++i) {
-      const double v = cs.h1d[i] + cs.h2d[i];
-      hcol[i] = v;
-      hraw[i] = v;
+  const int t = threadIdx.x;
+  for (int i = t; i <= jc; i += kBlock) {
+    s_col[i] = cs.h1d[i] + cs.h2d[i];
+    if (i < jc) {
+      s_c[i] = cs.cs[i];
+      s_s[i] = cs.sn[i];
     }
-    hcol[jc + 1] = beta;
-    hraw[jc + 1] = beta;
-    for (int i = jc + 2; i < ldh; ++i) {  // below the subdiagonal: exact zeros
-      hcol[i] = 0.0;
-      hraw[i] = 0.0;
-    }
+  }
+  if (t == 0) {
+    s_col[jc + 1] = beta;
+    s_g[jc] = cs.g[jc];
+  }
+  __syncthreads();
+  double* hraw = cs.Hraw + (size_t)jc * ldh;
+  for (int i = t; i < ldh; i += kBlock) hraw[i] = (i <= jc + 1) ? s_col[i] : 0.0;
+  __syncthreads();
+  if (t == 0) {
     for (int i = 0; i < jc; ++i) {
-      const double hi = hcol[i], hi1 = hcol[i + 1];
-      const double c = cs.cs[i], s = cs.sn[i];
-      hcol[i] = c * hi + s * hi1;
-      hcol[i + 1] = -s * hi + c * hi1;
+      const double hi = s_col[i], hi1 = s_col[i + 1];
+      const double c = s_c[i], s = s_s[i];
+      s_col[i] = c * hi + s * hi1;
+      s_col[i + 1] = -s * hi + c * hi1;
     }
-    const double a = hcol[jc], b = hcol[jc + 1];
+    const double a = s_col[jc], b = s_col[jc + 1];
     const double rho = hypot(a, b);
     double c = 1.0, s = 0.0;
     if (rho != 0.0) {
@@ -419,16 +478,17 @@ __device__ __forceinline__ void givens_tail(CycleState cs, int jc, int last_jc, 
     }
     cs.cs[jc] = c;
     cs.sn[jc] = s;
-    hcol[jc] = c * a + s * b;
-    hcol[jc + 1] = 0.0;
-    const double gj = cs.g[jc];
+    s_col[jc] = c * a + s * b;
+    s_col[jc + 1] = 0.0;
+    const double gj = s_g[jc];
     cs.g[jc + 1] = -s * gj;
     cs.g[jc] = c * gj;
-    const double res = fabs(cs.g[jc + 1]);
+    s_g[jc] = c * gj;
+    const double res = fabs(s * gj);
     Status* st = cs.st;
     st->res = res;
     const bool brk = !(beta > breakdown_thresh);
-    const bool nonfin = !isfinite(res) || !isfinite(beta) || !isfinite(hcol[jc]);
+    const bool nonfin = !isfinite(res) || !isfinite(beta) || !isfinite(s_col[jc]);
     const bool conv = st->stop_thresh >= 0.0 && res <= st->stop_thresh;
     if (brk) st->breakdown = 1;
     if (nonfin) st->nonfinite = 1;
@@ -441,19 +501,25 @@ __device__ __forceinline__ void givens_tail(CycleState cs, int jc, int last_jc, 
     s_finish = finish ? 1 : 0;
   }
   __syncthreads();
+  double* hcol = cs.H + (size_t)jc * ldh;
+  for (int i = t; i < ldh; i += kBlock) hcol[i] = (i <= jc + 1) ? s_col[i] : 0.0;
   if (!s_finish) return;
   const int k = jc + 1;
-  for (int i = threadIdx.x; i < k; i += kBlock) s_g[i] = cs.g[i];
+  for (int i = t; i < jc; i += kBlock) s_g[i] = cs.g[i];
   __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    if (threadIdx.x == 0) {
-      const double yi = s_g[i] / cs.H[(size_t)i * ldh + i];
+    if (t == 0) {
+      const double rii = (i == jc) ? s_col[jc] : cs.H[(size_t)i * ldh + i];
+      const double yi = s_g[i] / rii;
       cs.y[i] = yi;
       s_y = yi;
     }
     __syncthreads();
     const double yi = s_y;
-    for (int t = threadIdx.x; t < i; t += kBlock) s_g[t] -= cs.H[(size_t)i * ldh + t] * yi;
+    for (int r = t; r < i; r += kBlock) {
+      const double rri = (i == jc) ? s_col[r] : cs.H[(size_t)i * ldh + r];
+      s_g[r] -= rri * yi;
+    }
     __syncthreads();
   }
 }

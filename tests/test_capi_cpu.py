@@ -61,7 +61,10 @@ def test_argument_errors_before_device_work():
     # null matrix
     assert lib.gmres_solve(None, None, None, None, C.byref(p), None, 0, C.byref(res), None, None) == -1
     assert b"null matrix" in lib.gmr_last_error()
-    A = _capi.gmr_csr(10, 28, 1, 1, 1, 1)
+    A = _capi.gmr_csr(10, 28, 16, 32, 48, 1)
+    unaligned = _capi.gmr_csr(10, 28, 16, 36, 48, 1)
+    assert lib.spmv(C.byref(unaligned), 64, 128, None) == -1
+    assert b"aligned" in lib.gmr_last_error()
     bad = _capi.gmr_params(0, 1e-10, 100, 0, 0, 0, 0)
     assert lib.gmres_solve(C.byref(A), None, 8, 16, C.byref(bad), None, 0, C.byref(res), None, None) == -1
     bad = _capi.gmr_params(50, -1.0, 100, 0, 0, 0, 0)

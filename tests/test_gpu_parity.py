@@ -385,3 +385,61 @@ def test_poisoned_workspace_gives_identical_results(fill):
     x0, res0 = G.gmres_ir_solve(A, A32, t64(p.b), restart=15, max_iters=3000, P=P0, ws=ws0)
     assert np.array_equal(P32.roots(), P0.roots())
     assert res.converged and np.array_equal(host(x), host(x0))
+
+
+def test_config3_full_poly_ir_and_fp64_reach_1e10():
+    # 2D upwind convection-diffusion, n = 6.25M, GMRES(100)-IR with a float32
+    # degree-25 GMRES polynomial vs float64 GMRES(100) with a float64 one
+    say("config3 full: generating")
+    p = W.config3_convdiff()
+    assert p.A.n == 6250000 and p.A.nnz == 31240000
+    A = dev(p.A)
+    A32 = A.to_f32()
+    b = t64(p.b)
+    v0 = W.poly_start_vector(p.A.n, p.poly_seed)
+    say("config3 full: poly setup")
+    P32 = G.poly_prec_setup(A32, 25, t32(v0))
+    P64 = G.poly_prec_setup(A, 25, t64(v0))
+    assert P32.degree == 25 and P64.degree == 25
+    say("config3 full: GMRES-IR")
+    x, res = G.gmres_ir_solve(A, A32, b, restart=100, tol=1e-10, max_iters=5000, P=P32)
+    say("IR", res.status_name, res.iters, res.cycles, res.rel_res, res.seconds)
+    assert res.converged and res.iters % 100 == 0
+    xh = host(x)
+    assert np.linalg.norm(p.b - O.spmv(p.A, xh)) / np.linalg.norm(p.b) <= 1e-10
+    say("config3 full: FP64 GMRES")
+    x64, r64 = G.gmres_solve(A, b, restart=100, tol=1e-10, max_iters=5000, P=P64)
+    say("FP64", r64.status_name, r64.iters, r64.cycles, r64.rel_res, r64.seconds)
+    assert r64.converged
+    x64h = host(x64)
+    assert np.linalg.norm(p.b - O.spmv(p.A, x64h)) / np.linalg.norm(p.b) <= 1e-10
+    # IR needs at most a few more cycles than float64 GMRES (§III-B, Tables II and III)
+    assert res.iters <= r64.iters + 3 * 100
+
+
+@pytest.mark.parametrize("kind", ["ir", "f64", "ir_poly"])
+def test_graph_replay_matches_eager(kind):
+    # one restart cycle captured as a hipGraph and replayed every restart (with
+    # host synchronisation and copies between replays) gives the eager bits
+    say("graph replay", kind)
+    p = W.config3_convdiff(N=48, restart=12, degree=5) if kind == "ir_poly" else W.config2_laplace3d(N=22, restart=12)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    b = t64(p.b)
+    P = None
+    if kind == "ir_poly":
+        P = G.poly_prec_setup(A32, 5, t32(W.poly_start_vector(p.A.n, p.poly_seed)))
+    out = []
+    for graph in (False, True, True):
+        if kind == "f64":
+            x, r = G.gmres_solve(A, b, restart=12, max_iters=20000, graph=graph)
+        else:
+            x, r = G.gmres_ir_solve(A, A32, b, restart=12, max_iters=20000, P=P, graph=graph)
+        out.append((host(x), r))
+    for xg, rg in out[1:]:
+        assert rg.converged and rg.cycles == out[0][1].cycles and rg.iters == out[0][1].iters
+        assert np.array_equal(xg, out[0][0]) and rg.history == out[0][1].history
+    # a capped last cycle (max_iters not a multiple of m) is captured again
+    x1, r1 = G.gmres_ir_solve(A, A32, b, restart=12, max_iters=30, P=P, graph=False)
+    x2, r2 = G.gmres_ir_solve(A, A32, b, restart=12, max_iters=30, P=P, graph=True)
+    assert r1.iters == r2.iters == 30 and np.array_equal(host(x1), host(x2))
