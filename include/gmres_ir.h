@@ -189,6 +189,65 @@ gmr_status gmr_harmonic_ritz(int32_t k, const double* H, int32_t ldh, double* re
  * complex-conjugate pairs adjacent, positive imaginary part first. */
 gmr_status gmr_leja_order(int32_t k, double* re, double* im);
 
+/* ---------------------------------------------------------------------------
+ * Batched block GMRES-IR: many independent systems with 16 right-hand sides
+ * each (the paper's solver handles one right-hand side, §IV; this is the
+ * multi-system, multi-RHS growth of the same method).  Per system, the 16
+ * right-hand sides share one block Krylov space built with two block
+ * classical Gram-Schmidt passes (block CGS2, §III-A) on the FP32 matrix cores
+ * and Cholesky QR twice inside each block; the outer loop is GMRES-IR
+ * (Alg. 2) with float64 residuals and updates, each column scaled by its own
+ * residual norm.
+ * ------------------------------------------------------------------------- */
+typedef struct gmr_batch gmr_batch;  /* opaque, host-side: sizes and the tile table */
+
+typedef struct {
+  int32_t status;        /* gmr_status                                               */
+  int32_t cycles;        /* restart cycles run (of the slowest system)               */
+  int64_t block_iters;   /* block steps summed over systems and cycles               */
+  double max_rel_res;    /* max over systems and columns of ||b - A x|| / ||b||      */
+  double seconds;        /* wall time of the solve                                   */
+} gmr_batch_result;
+
+/* A batch of nsys systems whose orders are sys_rows[0..nsys-1] (host array);
+ * their matrices are the diagonal blocks, in order, of one block-diagonal CSR
+ * matrix with global column indices.  nrhs must be 16; restart m in [1, 64]
+ * block steps.  *out is released with batch_destroy. */
+gmr_status batch_create(int32_t nsys, const int32_t* sys_rows, int32_t nrhs, int32_t restart,
+                        gmr_batch** out);
+void batch_destroy(gmr_batch* b);
+
+/* Device workspace needed by batch_gmres_ir_solve, batch_autotune and batch_bcgs_step. */
+size_t batch_workspace_bytes(const gmr_batch* b);
+
+/* Tiling of the matrix-core kernels: rows per tile (multiple of 16, >= 256) and
+ * basis blocks accumulated per pass (4, 8 or 16). */
+gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_blocks);
+gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* group_blocks);
+
+/* Times the block Gram-Schmidt contraction pair for every candidate tiling on
+ * the batch's own workspace (its contents are overwritten), keeps the fastest
+ * and reports it (best_* may be NULL).  Synchronous. */
+gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,
+                          int32_t* best_group_blocks, double* best_ms, void* stream);
+
+/* Solve A X = B for all systems to ||b - A x|| / ||b|| <= tol per column.
+ * A64 / A32: the block-diagonal matrix in float64 / float32 (same pattern).
+ * B, X: device float64, rows x 16 row-major (X holds X0 on entry).
+ * Z: device float32, rows x 16 row-major, random columns that replace start
+ * columns which (nearly) depend on earlier ones.  sys_cycles (nsys) and
+ * sys_rel_res (nsys x 16): optional host outputs.  Synchronous. */
+gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr* A32, const double* B,
+                                double* X, const float* Z, double tol, int32_t max_cycles, void* ws,
+                                size_t ws_bytes, gmr_batch_result* res, int32_t* sys_cycles,
+                                double* sys_rel_res, void* stream);
+
+/* One block Gram-Schmidt pass on its own (for tests): C = V^T W per system
+ * (device float64 out, nsys x nblk x 16 x 16, C[s][b][i][c]) and W -= V C.
+ * Vin: device float32, nblk blocks of rows x 16 (block-major).  Asynchronous. */
+gmr_status batch_bcgs_step(gmr_batch* b, const float* Vin, int32_t nblk, float* W, double* C, void* ws,
+                           size_t ws_bytes, void* stream);
+
 const char* gmr_last_error(void);
 
 #ifdef __cplusplus

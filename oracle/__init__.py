@@ -10,3 +10,4 @@ GPU path; the two only meet through the seeded inputs of ``workloads``.
 from .krylov import (spmv, cgs2, apply_givens_column, back_substitute, gmres,  # noqa: F401
                      gmres_ir, GmresOutcome, arnoldi)
 from .poly import harmonic_ritz_values, leja_order, poly_roots, poly_apply  # noqa: F401
+from .block import block_arnoldi, block_gmres_ir, cholqr2, dependent_columns, spmm, start_block  # noqa: F401,E402

@@ -18,7 +18,7 @@ from ._capi import GMR_F32, GMR_F64, GmresError, PROF, check
 
 __all__ = ["DeviceCSR", "Poly", "SolveResult", "workspace_bytes", "alloc_workspace", "spmv",
            "cgs2_orth", "poly_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve",
-           "hessenberg_eigvals", "harmonic_ritz", "leja_order", "GmresError", "GMR_F32", "GMR_F64", "lib"]
+           "hessenberg_eigvals", "harmonic_ritz", "leja_order", "Batch", "GmresError", "GMR_F32", "GMR_F64", "lib"]
 
 
 def lib():
@@ -283,3 +283,69 @@ def leja_order(z: np.ndarray) -> np.ndarray:
     im = np.ascontiguousarray(np.imag(z), dtype=np.float64).copy()
     check(lib().gmr_leja_order(len(re), re.ctypes.data_as(C.c_void_p), im.ctypes.data_as(C.c_void_p)))
     return re + 1j * im
+
+
+class Batch:
+    """Batched block GMRES-IR over many systems with 16 right-hand sides each.
+
+    The systems are the diagonal blocks of one block-diagonal CSR matrix (global
+    column indices); multivectors are row-major (rows x 16)."""
+
+    def __init__(self, sys_rows, restart: int = 50, nrhs: int = 16):
+        rows = np.ascontiguousarray(np.asarray(sys_rows, dtype=np.int32))
+        h = C.c_void_p()
+        check(lib().batch_create(len(rows), rows.ctypes.data_as(C.c_void_p), nrhs, restart, C.byref(h)))
+        self._h = h
+        self.nsys = len(rows)
+        self.rows = int(rows.sum())
+        self.restart = restart
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self) -> int:
+        return int(lib().batch_workspace_bytes(self._h))
+
+    def set_tiling(self, tile_rows: int, group_blocks: int):
+        check(lib().batch_set_tiling(self._h, tile_rows, group_blocks))
+
+    def tiling(self):
+        t, g = C.c_int32(), C.c_int32()
+        check(lib().batch_get_tiling(self._h, C.byref(t), C.byref(g)))
+        return t.value, g.value
+
+    def autotune(self, ws: torch.Tensor):
+        t, g, ms = C.c_int32(), C.c_int32(), C.c_double()
+        check(lib().batch_autotune(self._h, _ptr(ws), ws.numel(), C.byref(t), C.byref(g), C.byref(ms),
+                                   _stream(ws.device)))
+        return t.value, g.value, ms.value
+
+    def solve(self, A64: DeviceCSR, A32: DeviceCSR, B: torch.Tensor, X: torch.Tensor, Z: torch.Tensor,
+              ws: torch.Tensor, tol: float = 1e-10, max_cycles: int = 100):
+        res = _capi.gmr_batch_result()
+        cyc = np.zeros(self.nsys, dtype=np.int32)
+        rel = np.zeros(self.nsys * 16)
+        s64, s32 = A64.struct(), A32.struct()
+        status = lib().batch_gmres_ir_solve(self._h, C.byref(s64), C.byref(s32), _ptr(B), _ptr(X), _ptr(Z),
+                                            float(tol), int(max_cycles), _ptr(ws), ws.numel(), C.byref(res),
+                                            cyc.ctypes.data_as(C.c_void_p), rel.ctypes.data_as(C.c_void_p),
+                                            _stream(B.device))
+        check(status)
+        return {"status": res.status, "status_name": _capi.STATUS.get(res.status, str(res.status)),
+                "cycles": res.cycles, "block_iters": res.block_iters, "max_rel_res": res.max_rel_res,
+                "seconds": res.seconds, "sys_cycles": cyc, "sys_rel_res": rel.reshape(self.nsys, 16)}
+
+    def bcgs_step(self, Vin: torch.Tensor, nblk: int, W: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
+        Cout = torch.empty((self.nsys, nblk, 16, 16), dtype=torch.float64, device=W.device)
+        check(lib().batch_bcgs_step(self._h, _ptr(Vin), nblk, _ptr(W), _ptr(Cout), _ptr(ws), ws.numel(),
+                                    _stream(W.device)))
+        return Cout
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass

@@ -22,7 +22,9 @@ PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_n
 EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "poly_prec_apply",
             "poly_prec_destroy", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
             "gmres_ir_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
-            "gmr_last_error"]
+            "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
+            "batch_set_tiling", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve",
+            "batch_bcgs_step"]
 
 
 class gmr_csr(C.Structure):
@@ -42,6 +44,11 @@ class gmr_result(C.Structure):
                 ("seconds", C.c_double), ("history_len", C.c_int32), ("reserved", C.c_int32),
                 ("prof_ms", C.c_double), ("prof_launches", C.c_int64),
                 ("prof_bytes", C.c_double)]
+
+
+class gmr_batch_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("cycles", C.c_int32), ("block_iters", C.c_int64),
+                ("max_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
 _lib = None
@@ -89,6 +96,24 @@ def load() -> C.CDLL:
     lib.gmr_harmonic_ritz.restype = st
     lib.gmr_leja_order.argtypes = [C.c_int32, P, P]
     lib.gmr_leja_order.restype = st
+    lib.batch_create.argtypes = [C.c_int32, P, C.c_int32, C.c_int32, C.POINTER(P)]
+    lib.batch_create.restype = st
+    lib.batch_destroy.argtypes = [P]
+    lib.batch_destroy.restype = None
+    lib.batch_workspace_bytes.argtypes = [P]
+    lib.batch_workspace_bytes.restype = C.c_size_t
+    lib.batch_set_tiling.argtypes = [P, C.c_int32, C.c_int32]
+    lib.batch_set_tiling.restype = st
+    lib.batch_get_tiling.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    lib.batch_get_tiling.restype = st
+    lib.batch_autotune.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_double), P]
+    lib.batch_autotune.restype = st
+    lib.batch_gmres_ir_solve.argtypes = [P, C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P, C.c_double,
+                                         C.c_int32, P, C.c_size_t, C.POINTER(gmr_batch_result), P, P, P]
+    lib.batch_gmres_ir_solve.restype = st
+    lib.batch_bcgs_step.argtypes = [P, P, C.c_int32, P, P, P, C.c_size_t, P]
+    lib.batch_bcgs_step.restype = st
     lib.gmr_last_error.argtypes = []
     lib.gmr_last_error.restype = C.c_char_p
     _lib = lib

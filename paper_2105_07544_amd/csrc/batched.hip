@@ -1,0 +1,1006 @@
+// Batched block GMRES(m)-IR: many independent sparse systems, each with P = 16
+// right-hand sides, solved together.
+//
+// The paper's solver handles one right-hand side (§IV).  Here every system's
+// P right-hand sides share one block Krylov space: the new block W = A V_j is
+// orthogonalised against the earlier blocks by two block classical
+// Gram-Schmidt passes (the block form of the CGS2 of §III-A) and within itself
+// by Cholesky QR done twice.  The block Gram-Schmidt products V^T W and V C
+// are dense contractions of shape (16 j x rows) x (rows x 16) and
+// (rows x 16 j) x (16 j x 16); they run on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32) with FP32 accumulation.  The outer loop is GMRES-IR
+// (Alg. 2) per system: float64 block residual B - A X, every column scaled by
+// its own residual norm, float64 update of X.  The block least-squares
+// problem is solved per system in float64 with block Householder reflectors.
+//
+// Work is described by a tile table: every system's rows are cut into tiles
+// of at most `tile_rows` rows; a kernel launch covers all tiles of all
+// systems and skips the systems that are converged or have broken down in the
+// current cycle.  Multivectors are row-major with 16 columns (64 bytes per
+// row), which is exactly the operand layout the 16x16x4 MFMA wants.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/gmres_ir.h"
+#include "device_common.hpp"
+#include "host_common.hpp"
+
+namespace gmr {
+namespace bat {
+
+constexpr int P = 16;          // right-hand sides per system = block size
+constexpr int PP = P * P;      // entries of a 16 x 16 block
+constexpr int kMaxBlocks = 65; // restart m <= 64 block steps
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+struct BTile { int sys, r0, nr, pad; };
+struct BSys { int row_off, n, tile_start, tile_count; };
+struct BState {
+  int active;      // some column still above the tolerance
+  int cycle_done;  // the current cycle ended (block breakdown)
+  int kblk;        // block columns completed in the current cycle
+  int failed;      // the start block could not be formed
+};
+
+__device__ __forceinline__ bool running(const BState& s) { return s.active && !s.cycle_done; }
+
+__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// SpMM (float32 inner): Y = A X for the tiles of running systems.  16 lanes per
+// row (one per right-hand side), 16 rows per block pass, nonzeros in ascending k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void bspmm_kernel(const BTile* __restrict__ tiles,
+                                                       const BState* __restrict__ st,
+                                                       const int* __restrict__ rp,
+                                                       const int* __restrict__ ci,
+                                                       const float* __restrict__ val,
+                                                       const float* __restrict__ X,
+                                                       float* __restrict__ Y) {
+  const BTile tl = tiles[blockIdx.x];
+  if (!running(st[tl.sys])) return;
+  const int c = threadIdx.x % P;
+  const int rs = threadIdx.x / P;
+  const int rend = tl.r0 + tl.nr;
+  for (int r = tl.r0 + rs; r < rend; r += kBlock / P) {
+    float acc = 0.f;
+    const int k1 = rp[r + 1];
+    for (int k = rp[r]; k < k1; ++k) acc += val[k] * X[(size_t)ci[k] * P + c];
+    Y[(size_t)r * P + c] = acc;
+  }
+}
+
+// Float64 block residual R = B - A X (X may be null: R = B) with per-tile,
+// per-column partial sums of squares in rpart[tile * 16 + c].
+__global__ __launch_bounds__(kBlock) void bresidual_kernel(const BTile* __restrict__ tiles,
+                                                           const BState* __restrict__ st,
+                                                           const int* __restrict__ rp,
+                                                           const int* __restrict__ ci,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ X,
+                                                           const double* __restrict__ B,
+                                                           double* __restrict__ R,
+                                                           double* __restrict__ rpart) {
+  __shared__ double s_sq[kBlock];
+  const BTile tl = tiles[blockIdx.x];
+  if (st && !st[tl.sys].active) return;
+  const int c = threadIdx.x % P;
+  const int rs = threadIdx.x / P;
+  const int rend = tl.r0 + tl.nr;
+  double sq = 0.0;
+  for (int r = tl.r0 + rs; r < rend; r += kBlock / P) {
+    double acc = 0.0;
+    if (X) {
+      const int k1 = rp[r + 1];
+      for (int k = rp[r]; k < k1; ++k) acc += val[k] * X[(size_t)ci[k] * P + c];
+    }
+    const double rv = B[(size_t)r * P + c] - acc;
+    R[(size_t)r * P + c] = rv;
+    sq += rv * rv;
+  }
+  s_sq[threadIdx.x] = sq;
+  __syncthreads();
+  if (threadIdx.x < P) {
+    double s = 0.0;
+    for (int g = 0; g < kBlock / P; ++g) s += s_sq[g * P + threadIdx.x];
+    rpart[(size_t)blockIdx.x * P + threadIdx.x] = s;
+  }
+}
+
+// Per system: the column norms from the tile partials (fixed order).
+// mode 0: bnorm = ||B||; mode 1: gam = ||R||, active = some column above tol.
+__global__ void bfinish_res_kernel(int nsys, const BSys* __restrict__ sys, BState* st,
+                                   const double* __restrict__ rpart, double* gam, double* bnorm,
+                                   double tol, int mode) {
+  const int s = blockIdx.x;
+  if (s >= nsys) return;
+  if (mode == 1 && !st[s].active) return;
+  __shared__ int s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  if (threadIdx.x < P) {
+    const int c = threadIdx.x;
+    double sum = 0.0;
+    for (int t = 0; t < sys[s].tile_count; ++t) sum += rpart[(size_t)(sys[s].tile_start + t) * P + c];
+    const double nrm = sqrt(sum);
+    if (mode == 0) {
+      bnorm[s * P + c] = nrm;
+    } else {
+      gam[s * P + c] = nrm;
+      const double bn = bnorm[s * P + c];
+      if (bn > 0.0 && !(nrm <= tol * bn)) atomicOr(&s_any, 1);
+    }
+  }
+  __syncthreads();
+  if (mode == 1 && threadIdx.x == 0) st[s].active = s_any;
+}
+
+// Start of a cycle: W = float(R / gamma_c) per column (0 for a column with gamma 0).
+__global__ __launch_bounds__(kBlock) void bstart_kernel(const BTile* __restrict__ tiles,
+                                                        const BState* __restrict__ st,
+                                                        const double* __restrict__ R,
+                                                        const double* __restrict__ gam,
+                                                        float* __restrict__ W) {
+  const BTile tl = tiles[blockIdx.x];
+  if (!running(st[tl.sys])) return;
+  const int c = threadIdx.x % P;
+  const double g = gam[tl.sys * P + c];
+  const double ig = g > 0.0 ? 1.0 / g : 0.0;
+  for (int r = tl.r0 + (int)threadIdx.x / P; r < tl.r0 + tl.nr; r += kBlock / P)
+    W[(size_t)r * P + c] = float(R[(size_t)r * P + c] * ig);
+}
+
+// ---------------------------------------------------------------------------
+// Block dots on the matrix cores: for the tile's rows, C_b = V_b^T W for the
+// nblk blocks V_b (b = 0..nblk-1), 16 x 16 each, into
+// partial[tile][b][i * 16 + c].  Operand A of one MFMA is V_b^T restricted to
+// 4 rows (lane l holds V_b[r + l/16][l % 16]), operand B is W on the same 4
+// rows (lane l holds W[r + l/16][l % 16]): both are one contiguous 256-byte
+// load.  The row sum is the MFMA's K accumulation; GB blocks are accumulated
+// per pass over the rows.
+// ---------------------------------------------------------------------------
+template <int GB>
+__global__ __launch_bounds__(kBlock) void bdots_kernel(const BTile* __restrict__ tiles,
+                                                       const BState* __restrict__ st,
+                                                       const float* __restrict__ V,
+                                                       size_t vstride, int nblk,
+                                                       const float* __restrict__ W,
+                                                       float* __restrict__ partial,
+                                                       size_t pstride) {
+  __shared__ float s_acc[kWavesPerBlock][GB][PP];
+  const BTile tl = tiles[blockIdx.x];
+  if (!running(st[tl.sys])) return;
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  const int rsub = lane / P;
+  const int col = lane % P;
+  const int rend = tl.r0 + tl.nr;
+  for (int g0 = 0; g0 < nblk; g0 += GB) {
+    floatx4 acc[GB];
+#pragma unroll
+    for (int b = 0; b < GB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int r = tl.r0 + 4 * wave; r < rend; r += 4 * kWavesPerBlock) {
+      const int row = r + rsub;
+      const bool ok = row < rend;
+      const float bw = ok ? W[(size_t)row * P + col] : 0.f;
+      float a[GB];
+#pragma unroll
+      for (int b = 0; b < GB; ++b)
+        a[b] = (ok && g0 + b < nblk) ? V[(size_t)(g0 + b) * vstride + (size_t)row * P + col] : 0.f;
+#pragma unroll
+      for (int b = 0; b < GB; ++b)
+        if (g0 + b < nblk) acc[b] = mfma16(a[b], bw, acc[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < GB; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s_acc[wave][b][(4 * rsub + q) * P + col] = acc[b][q];
+    __syncthreads();
+    for (int b = 0; b < GB && g0 + b < nblk; ++b) {
+      const int e = threadIdx.x;
+      float sum = s_acc[0][b][e];
+#pragma unroll
+      for (int w = 1; w < kWavesPerBlock; ++w) sum += s_acc[w][b][e];
+      partial[(size_t)blockIdx.x * pstride + (size_t)(g0 + b) * PP + e] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// Per system and block b: the tile partials added in tile order (float64),
+// stored as Cd[s][b][.] and rounded into Cf[s][b][.] (matrix-core operand).
+__global__ __launch_bounds__(kBlock) void bfinish_c_kernel(const BSys* __restrict__ sys,
+                                                           const BState* __restrict__ st,
+                                                           const float* __restrict__ partial,
+                                                           size_t pstride, double* Cd, float* Cf,
+                                                           size_t cstride) {
+  const int s = blockIdx.x;
+  const int b = blockIdx.y;
+  if (!running(st[s])) return;
+  const int e = threadIdx.x;
+  double sum = 0.0;
+  for (int t = 0; t < sys[s].tile_count; ++t)
+    sum += partial[(size_t)(sys[s].tile_start + t) * pstride + (size_t)b * PP + e];
+  Cd[(size_t)s * cstride + (size_t)b * PP + e] = sum;
+  if (Cf) Cf[(size_t)s * cstride + (size_t)b * PP + e] = float(sum);
+}
+
+// ---------------------------------------------------------------------------
+// Block update on the matrix cores: for 16-row groups of the tile,
+// D = sum_b V_b(rows) C_b with C_b[i][c] from Cf[s][b], then
+//   kSub: out -= D;  kSet: out = D (out may alias V when nblk = 1);
+//   kXupd: X64[row][c] += gamma_c * D for the columns still above tol.
+// Operand A: lane l holds V_b[r0 + l%16][4kk + l/16]; operand B: lane l holds
+// C_b[4kk + l/16][l%16]; result: lane l holds rows r0 + 4(l/16) + q, column l%16.
+// ---------------------------------------------------------------------------
+enum { kSub = 0, kSet = 1, kXupd = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__ tiles,
+                                                       const BState* __restrict__ st,
+                                                       const float* V, size_t vstride, int nblk_arg,
+                                                       const float* __restrict__ Cf, size_t cstride,
+                                                       float* out, double* __restrict__ X64,
+                                                       const double* __restrict__ gam,
+                                                       const double* __restrict__ bnorm, double tol) {
+  extern __shared__ float s_C[];  // nblk x 16 x 16 coefficients (dynamic)
+  const BTile tl = tiles[blockIdx.x];
+  const BState ss = st[tl.sys];
+  int nblk = nblk_arg;
+  if constexpr (MODE == kXupd) {
+    if (!ss.active || ss.kblk <= 0) return;
+    nblk = ss.kblk;
+  } else {
+    if (!running(ss)) return;
+  }
+  const float* C = Cf + (size_t)tl.sys * cstride;
+  for (int e = threadIdx.x; e < nblk * PP; e += kBlock) s_C[e] = C[e];
+  __syncthreads();
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  const int rend = tl.r0 + tl.nr;
+  bool upd_col = true;
+  double gc = 0.0;
+  if constexpr (MODE == kXupd) {
+    const int c = lane % P;
+    gc = gam[tl.sys * P + c];
+    upd_col = !(gc <= tol * bnorm[tl.sys * P + c]);
+  }
+  for (int r0 = tl.r0 + 16 * wave; r0 < rend; r0 += 16 * kWavesPerBlock) {
+    const int arow = r0 + lane % 16;
+    const bool aok = arow < rend;
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < nblk; ++b) {
+      const float* Vb = V + (size_t)b * vstride + (size_t)arow * P;
+      float a[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) a[kk] = aok ? Vb[4 * kk + lane / 16] : 0.f;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        acc = mfma16(a[kk], s_C[b * PP + (4 * kk + lane / 16) * P + lane % 16], acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = r0 + 4 * (lane / 16) + q;
+      if (row < rend) {
+        const size_t idx = (size_t)row * P + lane % 16;
+        if constexpr (MODE == kSub) out[idx] -= acc[q];
+        else if constexpr (MODE == kSet) out[idx] = acc[q];
+        else if (upd_col) X64[idx] += gc * double(acc[q]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small per-system dense steps (float64)
+// ---------------------------------------------------------------------------
+// Columns of W that (nearly) depend on earlier ones, from G = W^T W (the
+// Cholesky factorisation that skips a column whose pivot is <= tau G_cc).
+__global__ void bdep_kernel(int nsys, const BState* __restrict__ st, const double* __restrict__ Gd,
+                            size_t gstride, int* depmask, double tau) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys || !running(st[s])) return;
+  const double* G = Gd + (size_t)s * gstride;
+  double R[PP];
+  for (int e = 0; e < PP; ++e) R[e] = 0.0;
+  int mask = 0;
+  for (int c = 0; c < P; ++c) {
+    double d = G[c * P + c];
+    for (int k = 0; k < c; ++k) d -= R[k * P + c] * R[k * P + c];
+    if (!(d > tau * G[c * P + c])) {
+      mask |= 1 << c;
+      continue;
+    }
+    const double rcc = sqrt(d);
+    R[c * P + c] = rcc;
+    for (int q = c + 1; q < P; ++q) {
+      double v = G[c * P + q];
+      for (int k = 0; k < c; ++k) v -= R[k * P + c] * R[k * P + q];
+      R[c * P + q] = v / rcc;
+    }
+  }
+  depmask[s] = mask;
+}
+
+// T = W with the flagged columns taken from the random block Z.
+__global__ __launch_bounds__(kBlock) void breplace_kernel(const BTile* __restrict__ tiles,
+                                                          const BState* __restrict__ st,
+                                                          const int* __restrict__ depmask,
+                                                          const float* __restrict__ W,
+                                                          const float* __restrict__ Z,
+                                                          float* __restrict__ T) {
+  const BTile tl = tiles[blockIdx.x];
+  if (!running(st[tl.sys])) return;
+  const int c = threadIdx.x % P;
+  const bool dep = (depmask[tl.sys] >> c) & 1;
+  for (int r = tl.r0 + (int)threadIdx.x / P; r < tl.r0 + tl.nr; r += kBlock / P) {
+    const size_t i = (size_t)r * P + c;
+    T[i] = dep ? Z[i] : W[i];
+  }
+}
+
+// Cholesky G = R^T R (R upper) and Rinv = R^{-1} (float32, matrix-core operand).
+// A pivot <= tau G_cc (or non-finite) ends the system's cycle (breakdown), or
+// marks the start block as failed when `start` is set.  When Rprev is given,
+// Rout = R Rprev (the two Cholesky QR passes combined).
+__global__ void bchol_kernel(int nsys, BState* st, const double* __restrict__ Gd, size_t gstride,
+                             const double* __restrict__ Rprev, double* __restrict__ Rout,
+                             float* __restrict__ Rinv_f, size_t rstride, double tau, int start) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys || !running(st[s])) return;
+  const double* G = Gd + (size_t)s * gstride;
+  double R[PP], Ri[PP];
+  for (int e = 0; e < PP; ++e) R[e] = Ri[e] = 0.0;
+  bool ok = true;
+  for (int c = 0; c < P && ok; ++c) {
+    double d = G[c * P + c];
+    for (int k = 0; k < c; ++k) d -= R[k * P + c] * R[k * P + c];
+    if (!(d > tau * G[c * P + c]) || !isfinite(d)) {
+      ok = false;
+      break;
+    }
+    const double rcc = sqrt(d);
+    R[c * P + c] = rcc;
+    for (int q = c + 1; q < P; ++q) {
+      double v = G[c * P + q];
+      for (int k = 0; k < c; ++k) v -= R[k * P + c] * R[k * P + q];
+      R[c * P + q] = v / rcc;
+    }
+  }
+  if (!ok) {
+    st[s].cycle_done = 1;
+    if (start) st[s].failed = 1;
+    return;
+  }
+  // upper-triangular inverse, column by column
+  for (int c = 0; c < P; ++c) {
+    Ri[c * P + c] = 1.0 / R[c * P + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int k = i + 1; k <= c; ++k) v += R[i * P + k] * Ri[k * P + c];
+      Ri[i * P + c] = -v / R[i * P + i];
+    }
+  }
+  float* Rf = Rinv_f + (size_t)s * rstride;
+  for (int e = 0; e < PP; ++e) Rf[e] = float(Ri[e]);
+  if (Rout) {
+    double* Ro = Rout + (size_t)s * PP;
+    if (Rprev) {
+      const double* Rp = Rprev + (size_t)s * PP;
+      for (int i = 0; i < P; ++i)
+        for (int c = 0; c < P; ++c) {
+          double v = 0.0;
+          for (int k = i; k <= c; ++k) v += R[i * P + k] * Rp[k * P + c];
+          Ro[i * P + c] = v;
+        }
+    } else {
+      for (int e = 0; e < PP; ++e) Ro[e] = R[e];
+    }
+  }
+}
+
+// Reset of the per-cycle state and of the right-hand side of the block least
+// squares problem: Grhs = [R0; 0] with R0 = V0^T W in Cd.
+__global__ void bcycle_reset_kernel(int nsys, BState* st) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys) return;
+  st[s].cycle_done = 0;
+  st[s].kblk = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void binit_rhs_kernel(const BState* __restrict__ st,
+                                                           const double* __restrict__ R0d,
+                                                           size_t cstride, double* Grhs,
+                                                           size_t gstride) {
+  const int s = blockIdx.x;
+  if (!running(st[s])) return;
+  double* G = Grhs + (size_t)s * gstride;
+  for (size_t e = threadIdx.x; e < gstride; e += kBlock) G[e] = (e < PP) ? R0d[(size_t)s * cstride + e] : 0.0;
+}
+
+// One block column of the block Hessenberg matrix, [C1 + C2; R], reduced by the
+// earlier block Householder reflectors, then a new set of 16 reflectors on its
+// 32 x 16 panel; the same reflectors are applied to Grhs.  Lane c of the
+// single wave owns column c.  Reflector t of block column i acts on rows
+// 16 i + t .. 16 i + 31 and is stored as v (v_t = 1) with its tau.
+__global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const double* __restrict__ C1d,
+                                                    const double* __restrict__ C2d, size_t cstride,
+                                                    const double* __restrict__ Rn, double* Hq,
+                                                    size_t hstride, int ldh, double* refl,
+                                                    double* tauv, size_t rfstride, double* Grhs,
+                                                    size_t gstride) {
+  const int s = blockIdx.x;
+  if (!running(st[s])) return;
+  __shared__ double s_v[32];
+  __shared__ double s_tau;
+  const int c = threadIdx.x;
+  double* H = Hq + (size_t)s * hstride;
+  double* RF = refl + (size_t)s * rfstride * 32;   // [blockcol][32 rows][16 refl]
+  double* TU = tauv + (size_t)s * rfstride;       // [blockcol][16]
+  double* G = Grhs + (size_t)s * gstride;          // [row][16]
+  double* hc = H + (size_t)(16 * j + (c < P ? c : 0)) * ldh;
+  if (c < P) {
+    for (int b = 0; b <= j; ++b)
+      for (int i = 0; i < P; ++i) {
+        const size_t e = (size_t)s * cstride + (size_t)b * PP + i * P + c;
+        hc[16 * b + i] = C1d[e] + C2d[e];
+      }
+    for (int i = 0; i < P; ++i) hc[16 * (j + 1) + i] = Rn[(size_t)s * PP + i * P + c];
+    for (int i = 16 * (j + 2); i < ldh; ++i) hc[i] = 0.0;
+    // earlier reflectors
+    for (int bi = 0; bi < j; ++bi) {
+      const double* V = RF + (size_t)bi * 32 * P;
+      for (int t = 0; t < P; ++t) {
+        const double tau = TU[bi * P + t];
+        if (tau == 0.0) continue;
+        double dot = hc[16 * bi + t];
+        for (int r = t + 1; r < 32; ++r) dot += V[r * P + t] * hc[16 * bi + r];
+        dot *= tau;
+        hc[16 * bi + t] -= dot;
+        for (int r = t + 1; r < 32; ++r) hc[16 * bi + r] -= dot * V[r * P + t];
+      }
+    }
+  }
+  __syncthreads();
+  // new reflectors on the panel rows 16 j .. 16 j + 31
+  double* Vn = RF + (size_t)j * 32 * P;
+  for (int t = 0; t < P; ++t) {
+    if (c == t) {
+      const double alpha = hc[16 * j + t];
+      double xn2 = 0.0;
+      for (int r = t + 1; r < 32; ++r) xn2 += hc[16 * j + r] * hc[16 * j + r];
+      double tau = 0.0;
+      double beta = alpha;
+      if (xn2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        const double sc = 1.0 / (alpha - beta);
+        for (int r = t + 1; r < 32; ++r) {
+          const double v = hc[16 * j + r] * sc;
+          s_v[r] = v;
+          Vn[r * P + t] = v;
+          hc[16 * j + r] = 0.0;
+        }
+      } else {
+        for (int r = t + 1; r < 32; ++r) {
+          s_v[r] = 0.0;
+          Vn[r * P + t] = 0.0;
+        }
+      }
+      hc[16 * j + t] = beta;
+      s_tau = tau;
+      TU[j * P + t] = tau;
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    if (tau != 0.0) {
+      if (c > t && c < P) {
+        double dot = hc[16 * j + t];
+        for (int r = t + 1; r < 32; ++r) dot += s_v[r] * hc[16 * j + r];
+        dot *= tau;
+        hc[16 * j + t] -= dot;
+        for (int r = t + 1; r < 32; ++r) hc[16 * j + r] -= dot * s_v[r];
+      }
+      if (c < P) {
+        double dot = G[(size_t)(16 * j + t) * P + c];
+        for (int r = t + 1; r < 32; ++r) dot += s_v[r] * G[(size_t)(16 * j + r) * P + c];
+        dot *= tau;
+        G[(size_t)(16 * j + t) * P + c] -= dot;
+        for (int r = t + 1; r < 32; ++r) G[(size_t)(16 * j + r) * P + c] -= dot * s_v[r];
+      }
+    }
+    __syncthreads();
+  }
+  if (c == 0) st[s].kblk = j + 1;
+}
+
+// Y = R^{-1} G over the K = 16 kblk leading rows (column-oriented
+// back-substitution), rounded into Yf[s][b][i * 16 + c] (row 16 b + i).
+__global__ __launch_bounds__(kBlock) void bbacksolve_kernel(const BState* __restrict__ st,
+                                                            const double* __restrict__ Hq,
+                                                            size_t hstride, int ldh, double* Grhs,
+                                                            size_t gstride, float* Yf,
+                                                            size_t ystride) {
+  const int s = blockIdx.x;
+  const BState ss = st[s];
+  if (!ss.active || ss.kblk <= 0) return;
+  const int K = 16 * ss.kblk;
+  const double* H = Hq + (size_t)s * hstride;
+  double* G = Grhs + (size_t)s * gstride;
+  float* Y = Yf + (size_t)s * ystride;
+  const int c = threadIdx.x % P;
+  const int rg = threadIdx.x / P;
+  for (int i = K - 1; i >= 0; --i) {
+    if (threadIdx.x < P) {
+      const double y = G[(size_t)i * P + c] / H[(size_t)i * ldh + i];
+      G[(size_t)i * P + c] = y;
+      Y[(size_t)i * P + c] = float(y);
+    }
+    __syncthreads();
+    const double y = G[(size_t)i * P + c];
+    for (int r = rg; r < i; r += kBlock / P) G[(size_t)r * P + c] -= H[(size_t)i * ldh + r] * y;
+    __syncthreads();
+  }
+}
+
+}  // namespace bat
+}  // namespace gmr
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+using namespace gmr;
+using namespace gmr::bat;
+
+struct gmr_batch {
+  int nsys = 0;
+  int m = 0;
+  int tile_rows = 1024;
+  int gb = 8;
+  int64_t rows = 0;
+  std::vector<int> sys_rows;
+  std::vector<BSys> sys;
+  std::vector<BTile> tiles;
+  int max_tiles = 0;  // tile count at the smallest tile size (workspace sizing)
+};
+
+namespace {
+
+#define BH(call)                                                                          \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return gmr::fail(GMR_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+#define BT(expr)                    \
+  do {                              \
+    gmr_status s_ = (expr);         \
+    if (s_ != GMR_OK) return s_;    \
+  } while (0)
+
+constexpr int kMinTileRows = 256;
+inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+void build_tiles(gmr_batch* b, int tile_rows) {
+  b->tile_rows = tile_rows;
+  b->tiles.clear();
+  b->sys.resize(b->nsys);
+  int64_t off = 0;
+  for (int s = 0; s < b->nsys; ++s) {
+    BSys& y = b->sys[s];
+    y.row_off = (int)off;
+    y.n = b->sys_rows[s];
+    y.tile_start = (int)b->tiles.size();
+    for (int r = 0; r < y.n; r += tile_rows) b->tiles.push_back({s, (int)off + r, std::min(tile_rows, y.n - r), 0});
+    y.tile_count = (int)b->tiles.size() - y.tile_start;
+    off += y.n;
+  }
+}
+
+int count_tiles(const gmr_batch* b, int tile_rows) {
+  int t = 0;
+  for (int s = 0; s < b->nsys; ++s) t += (b->sys_rows[s] + tile_rows - 1) / tile_rows;
+  return t;
+}
+
+struct BLayout {
+  size_t tiles, sys, st, gam, bnorm, dep, V, W, T, R64, partial, rpart, C1d, C2d, Cd, Cf, R1, Rn,
+      Hq, refl, tau, Grhs, Yf, end;
+  size_t vstride, pstride, cstride, hstride, gstride, rfstride, ystride;
+  int ldh;
+};
+
+BLayout layout(const gmr_batch* b) {
+  BLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = al(o + bytes); return at; };
+  const int m = b->m;
+  const size_t rows = (size_t)b->rows;
+  L.vstride = rows * P;
+  L.pstride = (size_t)(m + 1) * PP;
+  L.cstride = (size_t)(m + 1) * PP;
+  L.ldh = 16 * (m + 1);
+  L.hstride = (size_t)L.ldh * 16 * m;
+  L.gstride = (size_t)L.ldh * P;
+  L.rfstride = (size_t)m * P;
+  L.ystride = (size_t)m * PP;
+  const size_t ns = b->nsys;
+  L.tiles = take((size_t)b->max_tiles * sizeof(BTile));
+  L.sys = take(ns * sizeof(BSys));
+  L.st = take(ns * sizeof(BState));
+  L.gam = take(ns * P * 8);
+  L.bnorm = take(ns * P * 8);
+  L.dep = take(ns * 4);
+  L.V = take((size_t)(m + 1) * L.vstride * 4);
+  L.W = take(L.vstride * 4);
+  L.T = take(L.vstride * 4);
+  L.R64 = take(L.vstride * 8);
+  L.partial = take((size_t)b->max_tiles * L.pstride * 4);
+  L.rpart = take((size_t)b->max_tiles * P * 8);
+  L.C1d = take(ns * L.cstride * 8);
+  L.C2d = take(ns * L.cstride * 8);
+  L.Cd = take(ns * L.cstride * 8);
+  L.Cf = take(ns * L.cstride * 4);
+  L.R1 = take(ns * PP * 8);
+  L.Rn = take(ns * PP * 8);
+  L.Hq = take(ns * L.hstride * 8);
+  L.refl = take(ns * L.rfstride * 32 * 8);
+  L.tau = take(ns * L.rfstride * 8);
+  L.Grhs = take(ns * L.gstride * 8);
+  L.Yf = take(ns * L.ystride * 4);
+  L.end = o;
+  return L;
+}
+
+struct BRun {
+  const gmr_batch* b;
+  BLayout L;
+  char* base;
+  hipStream_t s;
+  template <class T> T* at(size_t off) const { return (T*)(base + off); }
+  int ntiles() const { return (int)b->tiles.size(); }
+};
+
+gmr_status launch_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return gmr::fail(GMR_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return GMR_OK;
+}
+
+// C[s][b] = V_b^T W for b < nblk, summed per system into Cd (and Cf).
+gmr_status dots(const BRun& R, const float* V, int nblk, const float* W, double* Cd, float* Cf) {
+  const BTile* tl = R.at<BTile>(R.L.tiles);
+  const BState* st = R.at<BState>(R.L.st);
+  float* part = R.at<float>(R.L.partial);
+  switch (R.b->gb) {
+    case 4: bdots_kernel<4><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
+    case 16: bdots_kernel<16><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
+    default: bdots_kernel<8><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
+  }
+  BT(launch_check("bdots_kernel"));
+  bfinish_c_kernel<<<dim3(R.b->nsys, nblk), kBlock, 0, R.s>>>(R.at<BSys>(R.L.sys), st, part, R.L.pstride, Cd, Cf,
+                                                                R.L.cstride);
+  return launch_check("bfinish_c_kernel");
+}
+
+template <int MODE>
+gmr_status gemm(const BRun& R, const float* V, int nblk, const float* Cf, float* out, double* X64 = nullptr,
+                double tol = 0.0) {
+  bgemm_kernel<MODE><<<R.ntiles(), kBlock, (size_t)nblk * PP * sizeof(float), R.s>>>(R.at<BTile>(R.L.tiles), R.at<BState>(R.L.st), V, R.L.vstride,
+                                                     nblk, Cf, R.L.cstride, out, X64, R.at<double>(R.L.gam),
+                                                     R.at<double>(R.L.bnorm), tol);
+  return launch_check("bgemm_kernel");
+}
+
+gmr_status chol(const BRun& R, const double* Gd, const double* Rprev, double* Rout, double tau, int start) {
+  const int ns = R.b->nsys;
+  bchol_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, R.at<BState>(R.L.st), Gd, R.L.cstride, Rprev, Rout,
+                                               R.at<float>(R.L.Cf), R.L.cstride, tau, start);
+  return launch_check("bchol_kernel");
+}
+
+// Cholesky QR twice of T in place: on success T is orthonormal; the
+// orthonormal block is written to `dst`, and Rn = R2 R1 (when rn).
+gmr_status cholqr2(const BRun& R, float* T, float* dst, double tau, int start, bool rn) {
+  double* Cd = R.at<double>(R.L.Cd);
+  float* Cf = R.at<float>(R.L.Cf);
+  BT(dots(R, T, 1, T, Cd, nullptr));
+  BT(chol(R, Cd, nullptr, rn ? R.at<double>(R.L.R1) : nullptr, tau, start));
+  BT(gemm<kSet>(R, T, 1, Cf, T));
+  BT(dots(R, T, 1, T, Cd, nullptr));
+  BT(chol(R, Cd, rn ? R.at<double>(R.L.R1) : nullptr, rn ? R.at<double>(R.L.Rn) : nullptr, tau, start));
+  return gemm<kSet>(R, T, 1, Cf, dst);
+}
+
+gmr_status check_batch_csr(const gmr_csr* A, int dtype, int64_t rows) {
+  if (!A || A->dtype != dtype || A->n != rows || !A->row_ptr || !A->col_idx || !A->val)
+    return gmr::fail(GMR_ERR_INVALID, "batched: matrix does not match the batch (dtype or rows)");
+  return GMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gmr_status batch_create(int32_t nsys, const int32_t* sys_rows, int32_t nrhs, int32_t restart,
+                        gmr_batch** out) {
+  if (!out || !sys_rows || nsys <= 0) return gmr::fail(GMR_ERR_INVALID, "batch_create: bad arguments");
+  if (nrhs != P) return gmr::fail(GMR_ERR_UNSUPPORTED, "batch_create: the block size is 16 right-hand sides");
+  if (restart < 1 || restart > kMaxBlocks - 1)
+    return gmr::fail(GMR_ERR_UNSUPPORTED, "batch_create: restart must be in [1, 64]");
+  gmr_batch* b = new gmr_batch;
+  b->nsys = nsys;
+  b->m = restart;
+  b->sys_rows.assign(sys_rows, sys_rows + nsys);
+  int64_t rows = 0;
+  for (int s = 0; s < nsys; ++s) {
+    if (sys_rows[s] <= 0) {
+      delete b;
+      return gmr::fail(GMR_ERR_INVALID, "batch_create: every system needs rows > 0");
+    }
+    rows += sys_rows[s];
+  }
+  if (rows >= (int64_t)1 << 31) {
+    delete b;
+    return gmr::fail(GMR_ERR_UNSUPPORTED, "batch_create: total rows must fit int32");
+  }
+  b->rows = rows;
+  b->max_tiles = count_tiles(b, kMinTileRows);
+  build_tiles(b, 1024);
+  *out = b;
+  return GMR_OK;
+}
+
+void batch_destroy(gmr_batch* b) { delete b; }
+
+size_t batch_workspace_bytes(const gmr_batch* b) { return b ? layout(b).end : 0; }
+
+gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_blocks) {
+  if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: null batch");
+  if (tile_rows < kMinTileRows || tile_rows % 16 != 0)
+    return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: tile_rows must be a multiple of 16, >= 256");
+  if (group_blocks != 4 && group_blocks != 8 && group_blocks != 16)
+    return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: group_blocks must be 4, 8 or 16");
+  build_tiles(b, tile_rows);
+  b->gb = group_blocks;
+  return GMR_OK;
+}
+
+gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* group_blocks) {
+  if (!b || !tile_rows || !group_blocks) return gmr::fail(GMR_ERR_INVALID, "batch_get_tiling: null pointer");
+  *tile_rows = b->tile_rows;
+  *group_blocks = b->gb;
+  return GMR_OK;
+}
+
+static gmr_status upload_tables(const BRun& R) {
+  BH(hipMemcpyAsync(R.at<BTile>(R.L.tiles), R.b->tiles.data(), R.b->tiles.size() * sizeof(BTile),
+                    hipMemcpyHostToDevice, R.s));
+  BH(hipMemcpyAsync(R.at<BSys>(R.L.sys), R.b->sys.data(), R.b->sys.size() * sizeof(BSys),
+                    hipMemcpyHostToDevice, R.s));
+  return GMR_OK;
+}
+
+gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr* A32, const double* B,
+                                double* X, const float* Z, double tol, int32_t max_cycles, void* ws,
+                                size_t ws_bytes, gmr_batch_result* res, int32_t* sys_cycles,
+                                double* sys_rel_res, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!b || !B || !X || !Z || !res) return gmr::fail(GMR_ERR_INVALID, "batch_gmres_ir_solve: null argument");
+  if (!(tol > 0.0) || max_cycles < 1) return gmr::fail(GMR_ERR_INVALID, "batch_gmres_ir_solve: bad tol or max_cycles");
+  BT(check_batch_csr(A64, GMR_F64, b->rows));
+  BT(check_batch_csr(A32, GMR_F32, b->rows));
+  BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
+  if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_gmres_ir_solve: workspace too small");
+  const int ns = b->nsys;
+  const int m = b->m;
+  const int nt = R.ntiles();
+  BT(upload_tables(R));
+  BTile* tl = R.at<BTile>(R.L.tiles);
+  BSys* sy = R.at<BSys>(R.L.sys);
+  BState* st = R.at<BState>(R.L.st);
+  double* gam = R.at<double>(R.L.gam);
+  double* bnorm = R.at<double>(R.L.bnorm);
+  float* V = R.at<float>(R.L.V);
+  float* W = R.at<float>(R.L.W);
+  float* T = R.at<float>(R.L.T);
+  double* R64 = R.at<double>(R.L.R64);
+  double* rpart = R.at<double>(R.L.rpart);
+  double* Cd = R.at<double>(R.L.Cd);
+  double* C1d = R.at<double>(R.L.C1d);
+  double* C2d = R.at<double>(R.L.C2d);
+  float* Cf = R.at<float>(R.L.Cf);
+  std::vector<BState> hst(ns);
+  for (auto& h : hst) h = BState{1, 0, 0, 0};
+  BH(hipMemcpyAsync(st, hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
+  // ||B|| per column, then the residual of the initial X
+  bresidual_kernel<<<nt, kBlock, 0, R.s>>>(tl, nullptr, A64->row_ptr, A64->col_idx, (const double*)A64->val,
+                                           nullptr, B, R64, rpart);
+  BT(launch_check("bresidual_kernel"));
+  bfinish_res_kernel<<<ns, 64, 0, R.s>>>(ns, sy, st, rpart, gam, bnorm, tol, 0);
+  BT(launch_check("bfinish_res_kernel"));
+  auto residual = [&]() -> gmr_status {
+    bresidual_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, A64->row_ptr, A64->col_idx, (const double*)A64->val, X, B,
+                                             R64, rpart);
+    BT(launch_check("bresidual_kernel"));
+    bfinish_res_kernel<<<ns, 64, 0, R.s>>>(ns, sy, st, rpart, gam, bnorm, tol, 1);
+    return launch_check("bfinish_res_kernel");
+  };
+  BT(residual());
+  std::vector<int> cycles(ns, 0);
+  int total_cycles = 0;
+  int64_t block_iters = 0;
+  gmr_status status = GMR_NOT_CONVERGED;
+  for (int cyc = 0;; ++cyc) {
+    BH(hipMemcpyAsync(hst.data(), st, ns * sizeof(BState), hipMemcpyDeviceToHost, R.s));
+    BH(hipStreamSynchronize(R.s));
+    int active = 0, failed = 0;
+    for (int s = 0; s < ns; ++s) {
+      if (hst[s].failed) ++failed;
+      else if (hst[s].active) ++active;
+    }
+    if (cyc > 0)
+      for (int s = 0; s < ns; ++s)
+        if (hst[s].kblk > 0) block_iters += hst[s].kblk;
+    if (failed) {
+      status = GMR_ERR_NONFINITE;
+      gmr::fail(GMR_ERR_NONFINITE, "batch_gmres_ir_solve: a start block could not be orthonormalised");
+      break;
+    }
+    if (active == 0) {
+      status = GMR_OK;
+      break;
+    }
+    if (cyc >= max_cycles) break;
+    for (int s = 0; s < ns; ++s)
+      if (hst[s].active) ++cycles[s];
+    ++total_cycles;
+    // --- start block: W = R/gamma, dependent columns from Z, Cholesky QR twice
+    bcycle_reset_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, st);
+    bstart_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, R64, gam, W);
+    BT(launch_check("bstart_kernel"));
+    BT(dots(R, W, 1, W, Cd, nullptr));
+    bdep_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, st, Cd, R.L.cstride, R.at<int>(R.L.dep), 1e-5);
+    breplace_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, R.at<int>(R.L.dep), W, Z, T);
+    BT(launch_check("breplace_kernel"));
+    BT(cholqr2(R, T, V, 1e-5, 1, false));
+    BT(dots(R, V, 1, W, Cd, nullptr));  // R0 = V0^T W
+    binit_rhs_kernel<<<ns, kBlock, 0, R.s>>>(st, Cd, R.L.cstride, R.at<double>(R.L.Grhs), R.L.gstride);
+    BT(launch_check("binit_rhs_kernel"));
+    // --- m block steps
+    for (int j = 0; j < m; ++j) {
+      const int nb = j + 1;
+      bspmm_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, A32->row_ptr, A32->col_idx, (const float*)A32->val,
+                                           V + (size_t)j * R.L.vstride, W);
+      BT(launch_check("bspmm_kernel"));
+      BT(dots(R, V, nb, W, C1d, Cf));
+      BT(gemm<kSub>(R, V, nb, Cf, W));
+      BT(dots(R, V, nb, W, C2d, Cf));
+      BT(gemm<kSub>(R, V, nb, Cf, W));
+      BT(cholqr2(R, W, V + (size_t)(j + 1) * R.L.vstride, 1e-5, 0, true));
+      bls_kernel<<<ns, kWave, 0, R.s>>>(j, st, C1d, C2d, R.L.cstride, R.at<double>(R.L.Rn),
+                                        R.at<double>(R.L.Hq), R.L.hstride, R.L.ldh, R.at<double>(R.L.refl),
+                                        R.at<double>(R.L.tau), R.L.rfstride, R.at<double>(R.L.Grhs), R.L.gstride);
+      BT(launch_check("bls_kernel"));
+    }
+    // --- solution update and the next residual
+    float* Yf = R.at<float>(R.L.Yf);
+    bbacksolve_kernel<<<ns, kBlock, 0, R.s>>>(st, R.at<double>(R.L.Hq), R.L.hstride, R.L.ldh,
+                                              R.at<double>(R.L.Grhs), R.L.gstride, Yf, R.L.ystride);
+    BT(launch_check("bbacksolve_kernel"));
+    // the update reads C from Yf, laid out like the Gram-Schmidt coefficients
+    bgemm_kernel<kXupd><<<nt, kBlock, (size_t)m * PP * sizeof(float), R.s>>>(tl, st, V, R.L.vstride, 0, Yf,
+                                                                              R.L.ystride, nullptr, X, gam,
+                                                                              bnorm, tol);
+    BT(launch_check("bgemm_kernel<xupd>"));
+    BT(residual());
+  }
+  BH(hipStreamSynchronize(R.s));
+  std::vector<double> hg(ns * P), hb(ns * P);
+  BH(hipMemcpy(hg.data(), gam, ns * P * 8, hipMemcpyDeviceToHost));
+  BH(hipMemcpy(hb.data(), bnorm, ns * P * 8, hipMemcpyDeviceToHost));
+  double worst = 0.0;
+  for (int i = 0; i < ns * P; ++i) {
+    const double r = hb[i] > 0.0 ? hg[i] / hb[i] : 0.0;
+    worst = std::max(worst, r);
+    if (sys_rel_res) sys_rel_res[i] = r;
+  }
+  if (sys_cycles)
+    for (int s = 0; s < ns; ++s) sys_cycles[s] = cycles[s];
+  const auto t1 = std::chrono::steady_clock::now();
+  res->status = status;
+  res->cycles = total_cycles;
+  res->block_iters = block_iters;
+  res->max_rel_res = worst;
+  res->seconds = std::chrono::duration<double>(t1 - t0).count();
+  return status;
+}
+
+// Times the block Gram-Schmidt contraction pair (dots + update over nblk = m/2
+// blocks) for every candidate tiling on the batch's own buffers and keeps the
+// fastest.  The workspace is the solve's; its contents are overwritten.
+gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,
+                          int32_t* best_group_blocks, double* best_ms, void* stream) {
+  if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_autotune: null batch");
+  BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
+  if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_autotune: workspace too small");
+  const int ns = b->nsys;
+  std::vector<BState> hst(ns, BState{1, 0, 0, 0});
+  BH(hipMemcpyAsync(R.at<BState>(R.L.st), hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
+  BH(hipMemsetAsync(R.at<float>(R.L.V), 0, (size_t)(b->m + 1) * R.L.vstride * 4, R.s));
+  BH(hipMemsetAsync(R.at<float>(R.L.W), 0, R.L.vstride * 4, R.s));
+  BH(hipMemsetAsync(R.at<float>(R.L.Cf), 0, (size_t)ns * R.L.cstride * 4, R.s));
+  hipEvent_t e0, e1;
+  BH(hipEventCreate(&e0));
+  BH(hipEventCreate(&e1));
+  const int nb = std::max(1, b->m / 2);
+  const int cand_rows[] = {512, 1024, 2048, 4096};
+  const int cand_gb[] = {4, 8, 16};
+  double best = 1e30;
+  int bt = b->tile_rows, bg = b->gb;
+  gmr_status status = GMR_OK;
+  for (int tr : cand_rows) {
+    for (int g : cand_gb) {
+      build_tiles(b, tr);
+      b->gb = g;
+      if ((status = upload_tables(R)) != GMR_OK) break;
+      float ms = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {  // first repetition warms up
+        if (hipEventRecord(e0, R.s) != hipSuccess) { status = GMR_ERR_HIP; break; }
+        if ((status = dots(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd),
+                           R.at<float>(R.L.Cf))) != GMR_OK) break;
+        if ((status = gemm<kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))) != GMR_OK) break;
+        if (hipEventRecord(e1, R.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { status = GMR_ERR_HIP; break; }
+        float t = 0.f;
+        hipEventElapsedTime(&t, e0, e1);
+        if (rep > 0) ms += t;
+      }
+      if (status != GMR_OK) break;
+      if (ms < best) {
+        best = ms;
+        bt = tr;
+        bg = g;
+      }
+    }
+    if (status != GMR_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  build_tiles(b, bt);
+  b->gb = bg;
+  if (status != GMR_OK) return gmr::fail(status, "batch_autotune: a timed launch failed");
+  if (best_tile_rows) *best_tile_rows = bt;
+  if (best_group_blocks) *best_group_blocks = bg;
+  if (best_ms) *best_ms = best / 2.0;
+  return GMR_OK;
+}
+
+// Block dots and block update on their own, for the parity tests:
+// C[s][b] = V_b^T W (float64, ns x nblk x 16 x 16) and then W -= V C.
+gmr_status batch_bcgs_step(gmr_batch* b, const float* Vin, int32_t nblk, float* W, double* C, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (!b || !Vin || !W || !C || nblk < 1 || nblk > b->m + 1)
+    return gmr::fail(GMR_ERR_INVALID, "batch_bcgs_step: bad arguments");
+  BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
+  if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_bcgs_step: workspace too small");
+  const int ns = b->nsys;
+  std::vector<BState> hst(ns, BState{1, 0, 0, 0});
+  BH(hipMemcpyAsync(R.at<BState>(R.L.st), hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
+  BT(upload_tables(R));
+  BH(hipMemcpyAsync(R.at<float>(R.L.V), Vin, (size_t)nblk * R.L.vstride * 4, hipMemcpyDeviceToDevice, R.s));
+  BT(dots(R, R.at<float>(R.L.V), nblk, W, R.at<double>(R.L.Cd), R.at<float>(R.L.Cf)));
+  for (int s = 0; s < ns; ++s)
+    BH(hipMemcpyAsync(C + (size_t)s * nblk * PP, R.at<double>(R.L.Cd) + (size_t)s * R.L.cstride,
+                      (size_t)nblk * PP * 8, hipMemcpyDeviceToDevice, R.s));
+  return gemm<kSub>(R, R.at<float>(R.L.V), nblk, R.at<float>(R.L.Cf), W);
+}
+
+}  // extern "C"

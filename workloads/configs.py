@@ -17,7 +17,8 @@ from .prng import uniform01, uniform_pm1, uniform_int
 from .stencils import CSR, laplace2d, laplace3d, convdiff2d
 
 __all__ = ["Problem", "host_matvec", "config1_laplace2d", "config2_laplace3d",
-           "config3_convdiff", "config4_batch", "random_rhs", "poly_start_vector"]
+           "config3_convdiff", "config4_batch", "random_rhs", "poly_start_vector", "block_diag",
+           "stack_rows"]
 
 
 def host_matvec(A: CSR, x: np.ndarray) -> np.ndarray:
@@ -96,3 +97,25 @@ def config4_batch(count: int = 256, seed: int = 4, nrhs: int = 16, side_lo: int 
         B = random_rhs(s, A.n, nrhs, offset=3)
         systems.append(dict(A=A, B=B, N=N, eps=eps, phi=phi))
     return systems
+
+
+def block_diag(mats) -> CSR:
+    """One CSR matrix with the given matrices as diagonal blocks (global columns)."""
+    n = sum(A.n for A in mats)
+    nnz = sum(A.nnz for A in mats)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    r = c = 0
+    for A in mats:
+        row_ptr[r + 1:r + A.n + 1] = A.row_ptr[1:].astype(np.int64) + c
+        col[c:c + A.nnz] = A.col_idx + r
+        val[c:c + A.nnz] = A.val
+        r += A.n
+        c += A.nnz
+    return CSR(n, row_ptr.astype(np.int32), col, val)
+
+
+def stack_rows(blocks) -> np.ndarray:
+    """Row-major (rows x p) array from per-system (n_s x p) blocks."""
+    return np.ascontiguousarray(np.concatenate(blocks, axis=0))
