@@ -248,6 +248,39 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
 gmr_status batch_bcgs_step(gmr_batch* b, const float* Vin, int32_t nblk, float* W, double* C, void* ws,
                            size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Learned parameter predictor (restart length, polynomial degree and inner
+ * precision of GMRES-IR from cheap matrix features; the paper's guidance for
+ * these choices is §V-B, §V-C, §V-E and §V-F).  A 16-64-64-11 MLP, ReLU,
+ * three softmax heads (4 restarts, 5 degrees, 2 precisions); the parameters
+ * are one float32 vector: W1 (64x16, row-major), b1, W2 (64x64), b2,
+ * W3 (11x64), b3.  All pointers are device pointers unless stated.
+ * ------------------------------------------------------------------------- */
+int32_t mlp_param_count(void);                 /* 5963 */
+size_t mlp_workspace_bytes(int32_t batch);     /* for mlp_loss_grad */
+
+/* logits (batch x 11) of the standardised features (X - mu) / sigma (X: batch x 16). */
+gmr_status mlp_forward(const float* params, const float* X, const float* mu, const float* sigma,
+                       int32_t batch, float* logits, void* stream);
+
+/* Gradient (5963) and loss (1 float, nullable) of the mean over the batch of the
+ * summed head cross-entropies; labels: batch x 3 class indices.  Asynchronous. */
+gmr_status mlp_loss_grad(const float* params, const float* X, const float* mu, const float* sigma,
+                         const int32_t* labels, int32_t batch, float* grad, float* loss, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on params with moments m, v. */
+gmr_status mlp_adam_step(float* params, const float* grad, float* m, float* v, int32_t step, float lr,
+                         float beta1, float beta2, float eps, void* stream);
+
+/* Thirteen row statistics of A into the host array out: sum and min of the
+ * diagonal-dominance ratio |a_ii| / sum_{j!=i} |a_ij|, rows with ratio >= 1,
+ * rows with off-diagonal entries, min (a_ii - r_i), max (a_ii + r_i), max r_i,
+ * max |a_ii|, sum a_ii, sum a_ii^2, max nonzeros in a row, ||A||_F^2 and
+ * ||A - A^T||_F^2 (columns must ascend within a row).  ws: device,
+ * 13 * 8 * (min(ceil(n/256), 1024) + 1) bytes.  Synchronous. */
+gmr_status matrix_stats(const gmr_csr* A, double* out, void* ws, size_t ws_bytes, void* stream);
+
 const char* gmr_last_error(void);
 
 #ifdef __cplusplus

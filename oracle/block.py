@@ -67,12 +67,14 @@ def block_arnoldi(A, V0: np.ndarray, m: int, dt):
         C2 = Vj.T @ W
         W = W - Vj @ C2
         Q, R, ok = cholqr2(W)
-        if not ok:
-            # breakdown: the cycle ends with the j block columns built so far
-            break
         H[: (j + 1) * p, j * p:(j + 1) * p] = C1.astype(np.float64) + C2.astype(np.float64)
-        H[(j + 1) * p:(j + 2) * p, j * p:(j + 1) * p] = R
         k = j + 1
+        if not ok:
+            # breakdown: block column j is kept with the Cholesky factor that
+            # skips the dependent columns, and the cycle ends there
+            H[(j + 1) * p:(j + 2) * p, j * p:(j + 1) * p] = skip_cholesky((W.T @ W).astype(np.float64))[0]
+            break
+        H[(j + 1) * p:(j + 2) * p, j * p:(j + 1) * p] = R
         blocks.append(Q)
     return blocks, H[: (k + 1) * p, : k * p], k
 
@@ -80,10 +82,12 @@ def block_arnoldi(A, V0: np.ndarray, m: int, dt):
 DEP_TAU = 1e-5
 
 
-def dependent_columns(G: np.ndarray, tau: float = DEP_TAU) -> np.ndarray:
-    """Columns of W (Gram matrix G = W^T W) whose component orthogonal to the
-    earlier kept columns has relative squared norm <= tau: Cholesky of G that
-    skips such a column instead of stopping."""
+def skip_cholesky(G: np.ndarray, tau: float = DEP_TAU):
+    """Cholesky factor R (upper) of G = W^T W that skips, instead of stopping
+    at, a column whose pivot is at most tau times its squared norm: such a
+    column gets a zero row in R and is flagged dependent.  The columns of W
+    satisfy W = Q R for the orthonormal basis Q of the kept columns, up to the
+    skipped components."""
     p = G.shape[0]
     R = np.zeros((p, p))
     dep = np.zeros(p, dtype=bool)
@@ -91,10 +95,20 @@ def dependent_columns(G: np.ndarray, tau: float = DEP_TAU) -> np.ndarray:
         d = G[c, c] - np.sum(R[:c, c] ** 2)
         if not (d > tau * G[c, c]):
             dep[c] = True
+            R[c, c + 1:] = 0.0
             continue
         R[c, c] = np.sqrt(d)
         R[c, c + 1:] = (G[c, c + 1:] - R[:c, c] @ R[:c, c + 1:]) / R[c, c]
-    return dep
+    return R, dep
+
+
+def dependent_columns(G: np.ndarray, tau: float = DEP_TAU) -> np.ndarray:
+    """Columns of W (Gram matrix G = W^T W) whose component orthogonal to the
+    earlier kept columns has relative squared norm <= tau."""
+    return skip_cholesky(G, tau)[1]
+
+
+START_TAU = 1e-12
 
 
 def start_block(W: np.ndarray, Z: np.ndarray):
@@ -104,7 +118,7 @@ def start_block(W: np.ndarray, Z: np.ndarray):
     dep = dependent_columns((W.T @ W).astype(np.float64))
     Wp = W.copy()
     Wp[:, dep] = Z[:, dep].astype(W.dtype)
-    V0, _, ok = cholqr2(Wp)
+    V0, _, ok = cholqr2(Wp, START_TAU)
     R0 = (V0.T @ W).astype(np.float64)
     return V0, R0, ok, dep
 
@@ -144,7 +158,7 @@ def block_gmres_ir(A, B: np.ndarray, m: int, tol: float, max_cycles: int,
         E = np.zeros(((k + 1) * p, p))
         E[:p, :p] = R0
         Y = np.linalg.lstsq(Hbar, E, rcond=None)[0]
-        Vk = np.concatenate(blocks[:k], axis=1)
+        Vk = np.concatenate(blocks[:k], axis=1)  # the blocks that carry the solution
         U = (Vk @ Y.astype(f32)).astype(np.float64)
         X = X + U * gam
         cycles += 1

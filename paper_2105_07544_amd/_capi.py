@@ -24,7 +24,8 @@ EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "po
             "gmres_ir_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
             "batch_set_tiling", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve",
-            "batch_bcgs_step"]
+            "batch_bcgs_step", "mlp_param_count", "mlp_workspace_bytes", "mlp_forward",
+            "mlp_loss_grad", "mlp_adam_step", "matrix_stats"]
 
 
 class gmr_csr(C.Structure):
@@ -114,6 +115,18 @@ def load() -> C.CDLL:
     lib.batch_gmres_ir_solve.restype = st
     lib.batch_bcgs_step.argtypes = [P, P, C.c_int32, P, P, P, C.c_size_t, P]
     lib.batch_bcgs_step.restype = st
+    lib.mlp_param_count.argtypes = []
+    lib.mlp_param_count.restype = C.c_int32
+    lib.mlp_workspace_bytes.argtypes = [C.c_int32]
+    lib.mlp_workspace_bytes.restype = C.c_size_t
+    lib.mlp_forward.argtypes = [P, P, P, P, C.c_int32, P, P]
+    lib.mlp_forward.restype = st
+    lib.mlp_loss_grad.argtypes = [P, P, P, P, P, C.c_int32, P, P, P, C.c_size_t, P]
+    lib.mlp_loss_grad.restype = st
+    lib.mlp_adam_step.argtypes = [P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, P]
+    lib.mlp_adam_step.restype = st
+    lib.matrix_stats.argtypes = [C.POINTER(gmr_csr), P, P, C.c_size_t, P]
+    lib.matrix_stats.restype = st
     lib.gmr_last_error.argtypes = []
     lib.gmr_last_error.restype = C.c_char_p
     _lib = lib

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmresir.so")
-SOURCES = ["gmres_ir.hip", "batched.hip", "hessenberg.cpp"]
+SOURCES = ["gmres_ir.hip", "batched.hip", "predictor.hip", "hessenberg.cpp"]
 HEADERS = ["device_common.hpp", "kernels.hpp", "host_common.hpp"]
 
 HIPCC_FLAGS = [

@@ -42,12 +42,15 @@ struct BTile { int sys, r0, nr, pad; };
 struct BSys { int row_off, n, tile_start, tile_count; };
 struct BState {
   int active;      // some column still above the tolerance
-  int cycle_done;  // the current cycle ended (block breakdown)
+  int cycle_done;  // the current cycle ended (after a block breakdown)
   int kblk;        // block columns completed in the current cycle
   int failed;      // the start block could not be formed
+  int brk;         // the current block column broke down: it is the cycle's last
+  int pad;
 };
 
-__device__ __forceinline__ bool running(const BState& s) { return s.active && !s.cycle_done; }
+// A system whose block step is in progress.
+__device__ __forceinline__ bool running(const BState& s) { return s.active && !s.cycle_done && !s.brk; }
 
 __device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -348,24 +351,31 @@ __global__ __launch_bounds__(kBlock) void breplace_kernel(const BTile* __restric
 }
 
 // Cholesky G = R^T R (R upper) and Rinv = R^{-1} (float32, matrix-core operand).
-// A pivot <= tau G_cc (or non-finite) ends the system's cycle (breakdown), or
-// marks the start block as failed when `start` is set.  When Rprev is given,
-// Rout = R Rprev (the two Cholesky QR passes combined).
+// When Rprev is given, Rout = R Rprev (the two Cholesky QR passes combined).
+// A pivot <= tau G_cc (or non-finite) is handled by `mode`:
+//   kCholStart: the start block failed (the system stops);
+//   kCholPass1: breakdown of the block step; Rbrk receives the Cholesky factor
+//               that skips the dependent columns, and the block column is the
+//               cycle's last;
+//   kCholPass2: breakdown in the second pass; Rbrk receives Rprev.
+enum { kCholStart = 0, kCholPass1 = 1, kCholPass2 = 2 };
+
 __global__ void bchol_kernel(int nsys, BState* st, const double* __restrict__ Gd, size_t gstride,
                              const double* __restrict__ Rprev, double* __restrict__ Rout,
-                             float* __restrict__ Rinv_f, size_t rstride, double tau, int start) {
+                             float* __restrict__ Rinv_f, size_t rstride, double tau, int mode,
+                             double* __restrict__ Rbrk) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsys || !running(st[s])) return;
   const double* G = Gd + (size_t)s * gstride;
   double R[PP], Ri[PP];
   for (int e = 0; e < PP; ++e) R[e] = Ri[e] = 0.0;
   bool ok = true;
-  for (int c = 0; c < P && ok; ++c) {
+  for (int c = 0; c < P; ++c) {
     double d = G[c * P + c];
     for (int k = 0; k < c; ++k) d -= R[k * P + c] * R[k * P + c];
     if (!(d > tau * G[c * P + c]) || !isfinite(d)) {
       ok = false;
-      break;
+      continue;  // skip the column (zero row of R)
     }
     const double rcc = sqrt(d);
     R[c * P + c] = rcc;
@@ -376,8 +386,19 @@ __global__ void bchol_kernel(int nsys, BState* st, const double* __restrict__ Gd
     }
   }
   if (!ok) {
-    st[s].cycle_done = 1;
-    if (start) st[s].failed = 1;
+    if (mode == kCholStart) {
+      st[s].cycle_done = 1;
+      st[s].failed = 1;
+    } else {
+      double* Rb = Rbrk + (size_t)s * PP;
+      if (mode == kCholPass1) {
+        for (int e = 0; e < PP; ++e) Rb[e] = isfinite(R[e]) ? R[e] : 0.0;
+      } else {
+        const double* Rp = Rprev + (size_t)s * PP;
+        for (int e = 0; e < PP; ++e) Rb[e] = Rp[e];
+      }
+      st[s].brk = 1;
+    }
     return;
   }
   // upper-triangular inverse, column by column
@@ -414,6 +435,7 @@ __global__ void bcycle_reset_kernel(int nsys, BState* st) {
   if (s >= nsys) return;
   st[s].cycle_done = 0;
   st[s].kblk = 0;
+  st[s].brk = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void binit_rhs_kernel(const BState* __restrict__ st,
@@ -438,7 +460,7 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
                                                     double* tauv, size_t rfstride, double* Grhs,
                                                     size_t gstride) {
   const int s = blockIdx.x;
-  if (!running(st[s])) return;
+  if (!st[s].active || st[s].cycle_done) return;  // a block column that broke down is kept
   __shared__ double s_v[32];
   __shared__ double s_tau;
   const int c = threadIdx.x;
@@ -519,7 +541,13 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
     }
     __syncthreads();
   }
-  if (c == 0) st[s].kblk = j + 1;
+  if (c == 0) {
+    st[s].kblk = j + 1;
+    if (st[s].brk) {
+      st[s].cycle_done = 1;
+      st[s].brk = 0;
+    }
+  }
 }
 
 // Y = R^{-1} G over the K = 16 kblk leading rows (column-oriented
@@ -700,23 +728,28 @@ gmr_status gemm(const BRun& R, const float* V, int nblk, const float* Cf, float*
   return launch_check("bgemm_kernel");
 }
 
-gmr_status chol(const BRun& R, const double* Gd, const double* Rprev, double* Rout, double tau, int start) {
+gmr_status chol(const BRun& R, const double* Gd, const double* Rprev, double* Rout, double tau, int mode) {
   const int ns = R.b->nsys;
   bchol_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, R.at<BState>(R.L.st), Gd, R.L.cstride, Rprev, Rout,
-                                               R.at<float>(R.L.Cf), R.L.cstride, tau, start);
+                                               R.at<float>(R.L.Cf), R.L.cstride, tau, mode,
+                                               R.at<double>(R.L.Rn));
   return launch_check("bchol_kernel");
 }
 
 // Cholesky QR twice of T in place: on success T is orthonormal; the
-// orthonormal block is written to `dst`, and Rn = R2 R1 (when rn).
-gmr_status cholqr2(const BRun& R, float* T, float* dst, double tau, int start, bool rn) {
+// orthonormal block is written to `dst`, and, for a block step, Rn = R2 R1.
+// A start block uses only a positivity threshold (its dependent columns were
+// replaced before); a block step breaks down below tau.
+gmr_status cholqr2(const BRun& R, float* T, float* dst, double tau, bool start) {
   double* Cd = R.at<double>(R.L.Cd);
   float* Cf = R.at<float>(R.L.Cf);
+  const int m1 = start ? kCholStart : kCholPass1;
+  const int m2 = start ? kCholStart : kCholPass2;
   BT(dots(R, T, 1, T, Cd, nullptr));
-  BT(chol(R, Cd, nullptr, rn ? R.at<double>(R.L.R1) : nullptr, tau, start));
+  BT(chol(R, Cd, nullptr, start ? nullptr : R.at<double>(R.L.R1), tau, m1));
   BT(gemm<kSet>(R, T, 1, Cf, T));
   BT(dots(R, T, 1, T, Cd, nullptr));
-  BT(chol(R, Cd, rn ? R.at<double>(R.L.R1) : nullptr, rn ? R.at<double>(R.L.Rn) : nullptr, tau, start));
+  BT(chol(R, Cd, start ? nullptr : R.at<double>(R.L.R1), start ? nullptr : R.at<double>(R.L.Rn), tau, m2));
   return gemm<kSet>(R, T, 1, Cf, dst);
 }
 
@@ -819,7 +852,7 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
   double* C2d = R.at<double>(R.L.C2d);
   float* Cf = R.at<float>(R.L.Cf);
   std::vector<BState> hst(ns);
-  for (auto& h : hst) h = BState{1, 0, 0, 0};
+  for (auto& h : hst) h = BState{1, 0, 0, 0, 0, 0};
   BH(hipMemcpyAsync(st, hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
   // ||B|| per column, then the residual of the initial X
   bresidual_kernel<<<nt, kBlock, 0, R.s>>>(tl, nullptr, A64->row_ptr, A64->col_idx, (const double*)A64->val,
@@ -871,7 +904,7 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
     bdep_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, st, Cd, R.L.cstride, R.at<int>(R.L.dep), 1e-5);
     breplace_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, R.at<int>(R.L.dep), W, Z, T);
     BT(launch_check("breplace_kernel"));
-    BT(cholqr2(R, T, V, 1e-5, 1, false));
+    BT(cholqr2(R, T, V, 1e-12, true));
     BT(dots(R, V, 1, W, Cd, nullptr));  // R0 = V0^T W
     binit_rhs_kernel<<<ns, kBlock, 0, R.s>>>(st, Cd, R.L.cstride, R.at<double>(R.L.Grhs), R.L.gstride);
     BT(launch_check("binit_rhs_kernel"));
@@ -885,7 +918,7 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
       BT(gemm<kSub>(R, V, nb, Cf, W));
       BT(dots(R, V, nb, W, C2d, Cf));
       BT(gemm<kSub>(R, V, nb, Cf, W));
-      BT(cholqr2(R, W, V + (size_t)(j + 1) * R.L.vstride, 1e-5, 0, true));
+      BT(cholqr2(R, W, V + (size_t)(j + 1) * R.L.vstride, 1e-5, false));
       bls_kernel<<<ns, kWave, 0, R.s>>>(j, st, C1d, C2d, R.L.cstride, R.at<double>(R.L.Rn),
                                         R.at<double>(R.L.Hq), R.L.hstride, R.L.ldh, R.at<double>(R.L.refl),
                                         R.at<double>(R.L.tau), R.L.rfstride, R.at<double>(R.L.Grhs), R.L.gstride);
@@ -933,7 +966,7 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
   BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
   if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_autotune: workspace too small");
   const int ns = b->nsys;
-  std::vector<BState> hst(ns, BState{1, 0, 0, 0});
+  std::vector<BState> hst(ns, BState{1, 0, 0, 0, 0, 0});
   BH(hipMemcpyAsync(R.at<BState>(R.L.st), hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
   BH(hipMemsetAsync(R.at<float>(R.L.V), 0, (size_t)(b->m + 1) * R.L.vstride * 4, R.s));
   BH(hipMemsetAsync(R.at<float>(R.L.W), 0, R.L.vstride * 4, R.s));
@@ -992,7 +1025,7 @@ gmr_status batch_bcgs_step(gmr_batch* b, const float* Vin, int32_t nblk, float* 
   BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
   if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_bcgs_step: workspace too small");
   const int ns = b->nsys;
-  std::vector<BState> hst(ns, BState{1, 0, 0, 0});
+  std::vector<BState> hst(ns, BState{1, 0, 0, 0, 0, 0});
   BH(hipMemcpyAsync(R.at<BState>(R.L.st), hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
   BT(upload_tables(R));
   BH(hipMemcpyAsync(R.at<float>(R.L.V), Vin, (size_t)nblk * R.L.vstride * 4, hipMemcpyDeviceToDevice, R.s));

@@ -18,7 +18,7 @@ from .stencils import CSR, laplace2d, laplace3d, convdiff2d
 
 __all__ = ["Problem", "host_matvec", "config1_laplace2d", "config2_laplace3d",
            "config3_convdiff", "config4_batch", "random_rhs", "poly_start_vector", "block_diag",
-           "stack_rows"]
+           "stack_rows", "config5_systems"]
 
 
 def host_matvec(A: CSR, x: np.ndarray) -> np.ndarray:
@@ -119,3 +119,32 @@ def block_diag(mats) -> CSR:
 def stack_rows(blocks) -> np.ndarray:
     """Row-major (rows x p) array from per-system (n_s x p) blocks."""
     return np.ascontiguousarray(np.concatenate(blocks, axis=0))
+
+
+def config5_systems(count: int, seed: int = 5, side2d=(24, 128), side3d=(8, 24)):
+    """Systems for the parameter predictor: half upwind convection-diffusion
+    (diffusion 10^U(-3,0), random wind angle), a quarter 2D and a quarter 3D
+    Laplacians.  System i draws from stream seed ^ (i + 1): draw 1 the kind,
+    draw 2 the grid side, draws 3-4 diffusion and wind angle, then x_true."""
+    out = []
+    for i in range(count):
+        s = seed ^ (i + 1)
+        u = uniform01(s, 4)
+        kind = "convdiff" if u[0] < 0.5 else ("laplace2d" if u[0] < 0.75 else "laplace3d")
+        if kind == "laplace3d":
+            N = side3d[0] + min(int(u[1] * (side3d[1] - side3d[0] + 1)), side3d[1] - side3d[0])
+            A = laplace3d(N)
+            meta = dict(kind=kind, N=N)
+        else:
+            N = side2d[0] + min(int(u[1] * (side2d[1] - side2d[0] + 1)), side2d[1] - side2d[0])
+            if kind == "laplace2d":
+                A = laplace2d(N)
+                meta = dict(kind=kind, N=N)
+            else:
+                eps = float(10.0 ** (-3.0 + 3.0 * u[2]))
+                phi = float(2.0 * np.pi * u[3])
+                A = convdiff2d(N, eps, lambda x, y, p=phi: (np.cos(p), np.sin(p)))
+                meta = dict(kind=kind, N=N, eps=eps, phi=phi)
+        x_true = uniform_pm1(s, A.n, 4)
+        out.append(dict(A=A, b=host_matvec(A, x_true), x_true=x_true, seed=s, **meta))
+    return out
