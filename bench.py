@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark: time to a 1e-10 relative residual, GMRES-IR vs float64 GMRES, one MI355X.
 
-Workload: 3D 7-point Laplacian on a 150^3 grid (n = 3,375,000, nnz = 23,490,000,
-the size of the paper's Laplace3D150), b = A x_true with x_true ~ U(-1,1)
-(seed 2), x0 = 0, restart m = 50, tol 1e-10.  One step = one complete
-GMRES-IR solve (float32 inner GMRES(50) with CGS2, float64 residual and
-update) with the inputs already resident in HBM.  The float32 copy of A is
-made before the timed region (the paper excludes it too).
+Default workload (``--workload laplace3d``): 3D 7-point Laplacian on a 150^3 grid
+(n = 3,375,000, nnz = 23,490,000, the size of the paper's Laplace3D150),
+b = A x_true with x_true ~ U(-1,1) (seed 2), x0 = 0, restart m = 50, tol 1e-10.
+One step = one complete GMRES-IR solve (float32 inner GMRES(50) with CGS2,
+float64 residual and update) with the inputs already resident in HBM.  The
+float32 copy of A is made before the timed region (the paper excludes it too).
 
-Prints one JSON line.  Extra fields: the float64 GMRES(50) time on the same
-GPU and the ratio, per-kernel-family time and GB/s (the analogue of the
-paper's Table I), the roofline of the dominant kernel, and the oracle's
-time on the host CPU.
+Other workloads (each prints its own line; the default line is the one above):
+  convdiff   upwind convection-diffusion on 2500^2, GMRES(100)-IR with a float32
+             degree-25 GMRES polynomial vs float64 GMRES(100) with a float64 one
+  laplace2d  2D Laplacian 64^2, GMRES(50)
+  batch      256 convection-diffusion systems x 16 right-hand sides, batched
+             block GMRES(50)-IR on the matrix cores
+  predictor  the learned parameter predictor: label, train on the GPU, and
+             compare held-out time to solution with the fixed (m=50, d=0, f32)
+
+Extra fields: the float64 GMRES time on the same GPU and the ratio,
+per-kernel-family time and GB/s (the analogue of the paper's Table I), the
+roofline of the dominant kernel, and the oracle's time on the host CPU.
 """
 from __future__ import annotations
 
@@ -26,35 +34,43 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("time-to-1e-10 residual (GMRES-IR vs FP64 GMRES, same GPU); SpMV/CGS2 HBM GB/s")
 HBM_PEAK_GBS = 8000.0
-FAMILIES = ["spmv", "cgs_dots", "cgs_update_dots", "cgs_update_norm", "residual"]
-DOMINANT = "cgs_update_dots"
+FAMILIES = ["spmv", "cgs_dots", "cgs_update_dots", "cgs_update_norm", "poly_step", "residual"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(problem, iters_full: int, cycles_full: int, m: int):
-    """The oracle on the host: prefix runs of 1, 4 and 10 inner iterations of
-    the same solve fix a per-iteration cost a + b*j (j = basis size) and the
+def host_csr(A):
+    """scipy view of a CSR matrix, for the float64 residual checks on the host."""
+    import scipy.sparse as sp
+    return sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+
+
+def cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        return max(d.get("num_threads", 1) for d in info) if info else 1
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(problem, cycles_full: int, m: int, prec32=None, ks=(1, 4, 10)):
+    """The oracle on the host: prefix runs of a few inner iterations of the
+    same solve fix a per-iteration cost a + b*j (j = basis size) and the
     per-run overhead; the full solve is extrapolated to the GPU's cycle count."""
     import numpy as np
 
     import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max(d.get("num_threads", 1) for d in threadpool_info()) if threadpool_info() else 1
-    except Exception:
-        threads = os.cpu_count() or 1
     A, b = problem.A, problem.b
     t0 = time.perf_counter()
     O.spmv(A, b, np.float64)
     t_res = time.perf_counter() - t0
-    ks = [1, 4, 10]
     ts = []
     for k in ks:
         t0 = time.perf_counter()
-        O.gmres_ir(A, b, np.zeros(A.n), m, 1e-10, k)
+        O.gmres_ir(A, b, np.zeros(A.n), m, 1e-10, k, prec32=prec32)
         ts.append(time.perf_counter() - t0)
         log(f"cpu_baseline: oracle GMRES-IR prefix of {k} iterations: {ts[-1]:.2f} s")
     # T(k) = c0 + a k + b k(k+1)/2
@@ -62,86 +78,83 @@ def cpu_baseline(problem, iters_full: int, cycles_full: int, m: int):
     c0, a, bb = np.linalg.solve(M, np.array(ts))
     t_cycle = (c0 + a * m + bb * m * (m + 1) / 2.0) - t_res
     est = t_res + cycles_full * t_cycle
-    return {"value": float(est), "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"oracle GMRES-IR on the same workload, prefixes of {ks} inner iterations "
+    return {"value": float(est), "unit": "s", "cores": int(cpu_threads()), "kind": "oracle",
+            "sample": (f"oracle GMRES-IR on the same workload, prefixes of {list(ks)} inner iterations "
                        f"({sum(ts):.1f} s of CPU work); cost a+b*j per iteration and the "
                        f"per-run overhead fitted, extrapolated to {cycles_full} cycles of m={m}"),
             "sample_seconds": float(sum(ts))}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=150, help="grid side of the 3D Laplacian")
-    ap.add_argument("--restart", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-breakdown", action="store_true")
-    ap.add_argument("--graph", type=int, default=0,
-                    help="replay each restart cycle as a hipGraph (no per-kernel events then)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
-              "multi-GPU path; the sharded design is described in DESIGN.md", file=sys.stderr)
-        sys.exit(2)
-
+def single_system(args, kind):
     import numpy as np
     import torch
 
     import paper_2105_07544_amd as G
     import workloads as W
 
-    G.lib()  # fails loudly when the HIP library is not built
     dev = "cuda:0"
     log("bench: building the workload")
-    prob = W.config2_laplace3d(N=args.grid, restart=args.restart)
-    m = args.restart
+    if kind == "laplace3d":
+        N = args.grid or 150
+        prob = W.config2_laplace3d(N=N, restart=args.restart or 50)
+        desc = (f"GMRES({prob.restart})-IR, 3D Laplacian 6/-1 on {N}^3 (n={prob.A.n}, nnz={prob.A.nnz}), "
+                f"b=A*x_true, x_true~U(-1,1) seed 2, x0=0, tol 1e-10")
+    elif kind == "convdiff":
+        N = args.grid or 2500
+        prob = W.config3_convdiff(N=N, restart=args.restart or 100, degree=25)
+        desc = (f"GMRES({prob.restart})-IR + float32 GMRES polynomial of degree 25 vs float64 "
+                f"GMRES({prob.restart}) + float64 polynomial; upwind convection-diffusion eps=1e-3, wind "
+                f"(cos pi x, sin pi y) on {N}^2 (n={prob.A.n}, nnz={prob.A.nnz}), b=A*x_true seed 3, "
+                f"x0=0, tol 1e-10")
+    else:
+        N = args.grid or 64
+        prob = W.config1_laplace2d(N=N, restart=args.restart or 50)
+        desc = (f"GMRES({prob.restart})-IR vs float64 GMRES({prob.restart}), 2D Laplacian 4/-1 on {N}^2 "
+                f"(n={prob.A.n}), b=A*1, x0=0, tol 1e-10")
+    degree = prob.poly_degree
+    dominant = "poly_step" if degree else "cgs_update_dots"
+    m = prob.restart
     A64 = G.DeviceCSR.from_host(prob.A, dev)
     A32 = A64.to_f32()
     b = torch.from_numpy(prob.b).to(dev)
-    ws_ir = G.alloc_workspace(G.workspace_bytes(prob.A.n, m, G.GMR_F32), dev)
-    ws_64 = G.alloc_workspace(G.workspace_bytes(prob.A.n, m, G.GMR_F64), dev)
+    P32 = P64 = None
+    if degree:
+        v0 = W.poly_start_vector(prob.A.n, prob.poly_seed)
+        log("bench: polynomial setup (outside the timed region)")
+        P32 = G.poly_prec_setup(A32, degree, torch.from_numpy(v0.astype(np.float32)).to(dev))
+        P64 = G.poly_prec_setup(A64, degree, torch.from_numpy(v0).to(dev))
+    ws_ir = G.alloc_workspace(G.workspace_bytes(prob.A.n, m, G.GMR_F32, degree > 0), dev)
+    ws_64 = G.alloc_workspace(G.workspace_bytes(prob.A.n, m, G.GMR_F64, degree > 0), dev)
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
-
     graph = bool(args.graph)
 
-    def ir(prof="none"):
+    def ir(prof="none", g=None):
         x.zero_()
         return G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir,
-                                prof=prof, graph=graph)[1]
+                                P=P32, prof=prof, graph=graph if g is None else g)[1]
 
-    def f64(prof="none"):
+    def f64(prof="none", g=None):
         x.zero_()
-        return G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_64, prof=prof,
-                             graph=graph)[1]
+        return G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_64, P=P64,
+                             prof=prof, graph=graph if g is None else g)[1]
 
     log("bench: warmup")
     unprof = [ir().seconds for _ in range(args.warmup)]
     # timed region: K complete GMRES-IR solves; every launch of the dominant
     # kernel is bracketed by HIP events on the solver's stream (graph replay
-    # has no per-kernel events, so the timed solves launch eagerly unless
-    # --graph 1 is given, in which case K more eager solves give the roofline)
+    # has no per-kernel events, so with --graph 1 K more eager solves give them)
     log(f"bench: timing {args.steps} GMRES-IR solves")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = []
-    for _ in range(args.steps):
-        res.append(ir(prof="none" if graph else DOMINANT))
+    res = [ir(prof="none" if graph else dominant) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_ir = (time.perf_counter() - t0) / args.steps
-    if graph:
-        graph = False
-        pres = [ir(prof=DOMINANT) for _ in range(args.steps)]
-        graph = True
-    else:
-        pres = res
+    pres = [ir(prof=dominant, g=False) for _ in range(args.steps)] if graph else res
     last = res[-1]
     assert all(r.converged for r in res), [r.status_name for r in res]
     xh = x.cpu().numpy()
-    import oracle as O  # the explicit residual check runs in float64 on the host
-    rel = float(np.linalg.norm(prob.b - O.spmv(prob.A, xh)) / np.linalg.norm(prob.b))
+    rel = float(np.linalg.norm(prob.b - host_csr(prob.A) @ xh) / np.linalg.norm(prob.b))
     fwd = float(np.linalg.norm(xh - prob.x_true) / np.linalg.norm(prob.x_true))
     prof_ms = sum(r.prof_ms for r in pres)
     prof_bytes = sum(r.prof_bytes for r in pres)
@@ -152,50 +165,36 @@ def main():
     log("bench: float64 GMRES")
     f64()
     t0 = time.perf_counter()
-    r64 = []
-    for _ in range(max(1, min(args.steps, 3))):
-        r64.append(f64())
+    r64 = [f64() for _ in range(max(1, min(args.steps, 3)))]
     t_64 = (time.perf_counter() - t0) / len(r64)
-    assert all(r.converged for r in r64)
+    assert all(r.converged for r in r64), [r.status_name for r in r64]
 
     breakdown = {}
     if not args.no_breakdown:
         log("bench: per-kernel breakdown")
         for fam in FAMILIES:
-            ri = ir(prof=fam)
-            rd = f64(prof=fam)
+            if fam == "poly_step" and not degree:
+                continue
+            ri, rd = ir(prof=fam, g=False), f64(prof=fam, g=False)
             breakdown[fam] = {
                 "ir_ms": round(ri.prof_ms, 3), "ir_launches": ri.prof_launches,
                 "ir_gbs": round(ri.prof_bytes / (ri.prof_ms * 1e-3) / 1e9, 1) if ri.prof_ms > 0 else None,
                 "f64_ms": round(rd.prof_ms, 3), "f64_launches": rd.prof_launches,
                 "f64_gbs": round(rd.prof_bytes / (rd.prof_ms * 1e-3) / 1e9, 1) if rd.prof_ms > 0 else None,
             }
-
     out = {
-        "metric": METRIC,
-        "value": round(t_ir, 5),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(t_ir * 1e3, 3),
-        "higher_is_better": False,
-        "scaling": "strong",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"GMRES({m})-IR, 3D Laplacian 6/-1 on {args.grid}^3 (n={prob.A.n}, "
-                               f"nnz={prob.A.nnz}), b=A*x_true, x_true~U(-1,1) seed 2, x0=0, tol 1e-10",
-                   "n": prob.A.n, "nnz": prob.A.nnz, "restart": m, "tol": 1e-10,
-                   "inner": "f32", "outer": "f64"},
-        "fp64_gmres_s": round(t_64, 5),
-        "ir_speedup_vs_fp64": round(t_64 / t_ir, 3),
+        "metric": METRIC, "value": round(t_ir, 5), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_ir * 1e3, 3), "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": desc, "n": prob.A.n, "nnz": prob.A.nnz, "restart": m, "tol": 1e-10,
+                   "poly_degree": degree, "inner": "f32", "outer": "f64"},
+        "fp64_gmres_s": round(t_64, 5), "ir_speedup_vs_fp64": round(t_64 / t_ir, 3),
         "ir_iters": last.iters, "ir_cycles": last.cycles,
         "fp64_iters": r64[-1].iters, "fp64_cycles": r64[-1].cycles,
         "rel_res": rel, "forward_error": fwd,
         "ms_per_step_unprofiled": round(1e3 * float(np.median(unprof)), 3) if unprof else None,
-        "graph": bool(args.graph),
-        "roofline": {"kernel": DOMINANT, "bound": "hbm", "achieved": round(achieved, 1),
+        "graph": graph,
+        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launches": prof_launches,
                      "avg_launch_us": round(1e3 * prof_ms / max(1, prof_launches), 2),
@@ -204,7 +203,148 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(prob, last.iters, last.cycles, m)
+        prec32, ks = None, (1, 4, 10)
+        import oracle as O
+        if degree:
+            roots = P32.roots()
+            prec32 = lambda v: O.poly_apply(prob.A, roots, v, np.float32)  # noqa: E731
+            ks = (1, 2, 3)
+        out["cpu_baseline"] = cpu_baseline(prob, last.cycles, m, prec32, ks)
+    return out
+
+
+def batch(args):
+    import numpy as np
+    import torch
+
+    import paper_2105_07544_amd as G
+    import workloads as W
+
+    dev = "cuda:0"
+    log("bench: building 256 systems x 16 right-hand sides")
+    systems = W.config4_batch()
+    A = W.block_diag([s["A"] for s in systems])
+    B = W.stack_rows([s["B"] for s in systems])
+    Z = W.uniform_pm1(9, A.n * 16).reshape(A.n, 16).astype(np.float32)
+    A64 = G.DeviceCSR.from_host(A, dev)
+    A32 = A64.to_f32()
+    m = args.restart or 50
+    bt = G.Batch([s["A"].n for s in systems], restart=m)
+    ws = G.alloc_workspace(bt.workspace_bytes(), dev)
+    tiling = bt.autotune(ws)
+    log(f"bench: autotuned tiling {tiling}")
+    Bd = torch.from_numpy(B).to(dev)
+    Zd = torch.from_numpy(Z).to(dev)
+    X = torch.zeros_like(Bd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = bt.solve(A64, A32, Bd, X, Zd, ws, tol=1e-10, max_cycles=500)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    assert out["status"] == 0, out["status_name"]
+    Xh = X.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([s["A"].n for s in systems])])
+    worst = 0.0
+    for s in range(0, len(systems), 17):
+        sy = systems[s]
+        r = np.linalg.norm(sy["B"] - host_csr(sy["A"]) @ Xh[offs[s]:offs[s + 1]], axis=0)
+        worst = max(worst, float(np.max(r / np.linalg.norm(sy["B"], axis=0))))
+    return {"metric": METRIC, "value": round(t, 4), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": round(t * 1e3, 2), "higher_is_better": False, "scaling": "strong",
+            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": f"batched block GMRES({m})-IR, 256 upwind convection-diffusion systems "
+                                   f"(side U{{32..256}}, eps 10^U(-3,0), random wind angle) x 16 right-hand "
+                                   f"sides, rows={A.n}, nnz={A.nnz}, tol 1e-10 per column",
+                       "systems": len(systems), "rhs": 16, "rows": A.n, "nnz": A.nnz, "restart": m},
+            "rhs_solved_per_s": round(len(systems) * 16 / t, 2), "tiling": list(tiling[:2]),
+            "cycles_slowest_system": out["cycles"], "block_iters": out["block_iters"],
+            "max_rel_res": out["max_rel_res"], "sampled_host_rel_res": worst}
+
+
+def predictor(args):
+    import workloads as W
+    from paper_2105_07544_amd import predictor as PR
+
+    ntr, nte = args.train, args.test
+    train = W.config5_systems(ntr, seed=5)
+    test = W.config5_systems(nte, seed=6)
+    v_tr = [W.uniform_pm1(10000 + i, s["A"].n) for i, s in enumerate(train)]
+    v_te = [W.uniform_pm1(20000 + i, s["A"].n) for i, s in enumerate(test)]
+    t0 = time.perf_counter()
+    dtr = PR.build_dataset(train, v_tr, "cuda:0", log=log if args.verbose else None)
+    dte = PR.build_dataset(test, v_te, "cuda:0", log=log if args.verbose else None)
+    t_label = time.perf_counter() - t0
+    mu, sd = dtr.X.mean(0), dtr.X.std(0) + 1e-6
+    net = PR.Net(PR.init_params(23), mu, sd, "cuda:0")
+    epochs = 400
+    t0 = time.perf_counter()
+    hist = net.train(dtr.X, dtr.labels, epochs=epochs, batch=64, lr=3e-3, order_seed=700)
+    t_train = time.perf_counter() - t0
+    ev_tr, ev_te = PR.evaluate(net, dtr), PR.evaluate(net, dte)
+    ev_tr.pop("predictions")
+    ev_te.pop("predictions")
+    return {"metric": METRIC, "value": round(ev_te["total_pred"], 5), "unit": "s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": round(ev_te["total_pred"] * 1e3, 3),
+            "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"learned (m, degree, precision) predictor: {ntr} training and {nte} "
+                                   "held-out systems (half upwind convection-diffusion, a quarter 2D and a "
+                                   "quarter 3D Laplacians), 40 combinations timed per system",
+                       "train": ntr, "test": nte},
+            "held_out": ev_te, "train_fit": ev_tr, "fixed_baseline_total_s": ev_te["total_base"],
+            "gain_vs_fixed": round(ev_te["total_base"] / ev_te["total_pred"], 3),
+            "label_seconds": round(t_label, 2),
+            "train_samples_per_s": round(epochs * ntr / t_train, 1),
+            "loss_first_last": [hist[0], hist[-1]]}
+
+
+def copy_calibration(mib: int):
+    """Three plain device-to-device copies of `mib` MiB: under a hardware-counter
+    run their FETCH_SIZE / WRITE_SIZE give the scale factor from the counters
+    to bytes (each copy reads and writes exactly mib MiB)."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"bench: copy calibration, 3 copies of {mib} MiB")
+    del src, dst
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="laplace3d",
+                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor"])
+    ap.add_argument("--grid", type=int, default=0, help="grid side (0: the workload's own)")
+    ap.add_argument("--restart", type=int, default=0, help="restart length (0: the workload's own)")
+    ap.add_argument("--train", type=int, default=192, help="predictor: training systems")
+    ap.add_argument("--test", type=int, default=64, help="predictor: held-out systems")
+    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run three plain copies of MIB MiB first (counter scale factor)")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="replay each restart cycle as a hipGraph (no per-kernel events then)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
+              "multi-GPU path; the sharded design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import paper_2105_07544_amd as G
+    G.lib()  # fails loudly when the HIP library is not built
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+    if args.workload == "batch":
+        out = batch(args)
+    elif args.workload == "predictor":
+        out = predictor(args)
+    else:
+        out = single_system(args, args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -30,19 +30,9 @@ def unpack(theta: np.ndarray):
 
 
 def init_params(seed: int) -> np.ndarray:
-    """He-uniform weights and zero biases (the caller passes the random draws)."""
-    from workloads import uniform_pm1
-    parts = []
-    off = 0
-    for s in SHAPES:
-        k = int(np.prod(s))
-        if len(s) == 2:
-            lim = np.sqrt(6.0 / s[1])
-            parts.append(lim * uniform_pm1(seed, k, off))
-        else:
-            parts.append(np.zeros(k))
-        off += k
-    return np.concatenate(parts)
+    """He-uniform weights and zero biases (the seeded draws are an input)."""
+    from workloads import he_uniform_params
+    return he_uniform_params(seed, SHAPES)
 
 
 def forward(theta, X, mu, sigma):

@@ -35,6 +35,14 @@ PRECISIONS = ("f32", "f64")
 COMBOS = [(m, d, p) for m in RESTARTS for d in DEGREES for p in PRECISIONS]
 BASELINE = (50, 0, "f32")
 NFEAT = 16
+# layer shapes of the network, in the order of the flat parameter vector
+LAYERS = [(64, NFEAT), (64,), (64, 64), (64,), (11, 64), (11,)]
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-uniform initial weights (seeded draws), zero biases."""
+    from workloads import he_uniform_params
+    return he_uniform_params(seed, LAYERS)
 
 
 def _ptr(t):

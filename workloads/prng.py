@@ -59,3 +59,19 @@ def uniform_int(seed: int, lo: int, hi: int, count: int, offset: int = 0) -> np.
     """Integers uniform on ``{lo, ..., hi}`` (inclusive) by scaling a U[0,1) draw."""
     u = uniform01(seed, count, offset)
     return lo + np.minimum((u * (hi - lo + 1)).astype(np.int64), hi - lo)
+
+
+def he_uniform_params(seed: int, shapes) -> np.ndarray:
+    """Initial parameters of a dense network, flattened in the order of
+    ``shapes``: every 2-D weight (out x in) is U(-l, l) with l = sqrt(6 / in)
+    drawn from stream ``seed`` at the running offset; every 1-D bias is zero."""
+    parts = []
+    off = 0
+    for s in shapes:
+        k = int(np.prod(s))
+        if len(s) == 2:
+            parts.append(np.sqrt(6.0 / s[1]) * uniform_pm1(seed, k, off))
+        else:
+            parts.append(np.zeros(k))
+        off += k
+    return np.concatenate(parts)
