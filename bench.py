@@ -299,16 +299,19 @@ def predictor(args):
 
 
 def copy_calibration(mib: int):
-    """Three plain device-to-device copies of `mib` MiB: under a hardware-counter
-    run their FETCH_SIZE / WRITE_SIZE give the scale factor from the counters
-    to bytes (each copy reads and writes exactly mib MiB)."""
+    """Plain streaming kernels of known size, for a hardware-counter run: three
+    device-to-device copies and three element-wise negations of `mib` MiB, each
+    reading and writing exactly `mib` MiB.  Their FETCH_SIZE / WRITE_SIZE give
+    the scale factor from the counters to bytes."""
     import torch
     src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
     torch.cuda.synchronize()
-    log(f"bench: copy calibration, 3 copies of {mib} MiB")
+    log(f"bench: copy calibration, 3 copies and 3 negations of {mib} MiB")
     del src, dst
 
 

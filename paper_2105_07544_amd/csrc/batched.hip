@@ -240,8 +240,12 @@ __global__ __launch_bounds__(kBlock) void bfinish_c_kernel(const BSys* __restric
 // D = sum_b V_b(rows) C_b with C_b[i][c] from Cf[s][b], then
 //   kSub: out -= D;  kSet: out = D (out may alias V when nblk = 1);
 //   kXupd: X64[row][c] += gamma_c * D for the columns still above tol.
-// Operand A: lane l holds V_b[r0 + l%16][4kk + l/16]; operand B: lane l holds
-// C_b[4kk + l/16][l%16]; result: lane l holds rows r0 + 4(l/16) + q, column l%16.
+// The inner index i of V_b C_b is split as i = 4 g + kk (g = lane / 16, kk the
+// MFMA step): lane l loads V_b[r0 + l%16][4g .. 4g+3] as one 16-byte vector
+// (the wave reads 16 whole rows, 1 KB contiguous) and feeds element kk to step
+// kk, whose B operand is C_b[4g + kk][l%16].  The coefficients sit in LDS as
+// s_C[b][g][c][kk], so the four B values of a lane are one 16-byte LDS read.
+// Result: lane l holds rows r0 + 4(l/16) + q, column l%16.
 // ---------------------------------------------------------------------------
 enum { kSub = 0, kSet = 1, kXupd = 2 };
 
@@ -264,7 +268,10 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
     if (!running(ss)) return;
   }
   const float* C = Cf + (size_t)tl.sys * cstride;
-  for (int e = threadIdx.x; e < nblk * PP; e += kBlock) s_C[e] = C[e];
+  for (int e = threadIdx.x; e < nblk * PP; e += kBlock) {
+    const int b = e / PP, i = (e / P) % P, c = e % P;  // C_b[i][c], i = 4 g + kk
+    s_C[((b * 4 + i / 4) * P + c) * 4 + i % 4] = C[e];
+  }
   __syncthreads();
   const int lane = threadIdx.x % kWave;
   const int wave = threadIdx.x / kWave;
@@ -280,15 +287,31 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
     const int arow = r0 + lane % 16;
     const bool aok = arow < rend;
     floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < nblk; ++b) {
-      const float* Vb = V + (size_t)b * vstride + (size_t)arow * P;
-      float a[4];
+    const int g = lane / 16;
+    // two accumulators (even and odd b) so that consecutive MFMAs are independent
+    floatx4 acc1 = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* Vr = V + (size_t)arow * P + 4 * g;
+    const float* Cl = s_C + (g * P + lane % 16) * 4;
+    int b = 0;
+    for (; b + 1 < nblk; b += 2) {
+      const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
+      const floatx4 a0 = aok ? *(const floatx4*)(Vr + (size_t)b * vstride) : z;
+      const floatx4 a1 = aok ? *(const floatx4*)(Vr + (size_t)(b + 1) * vstride) : z;
+      const floatx4 c0 = *(const floatx4*)(Cl + b * PP);
+      const floatx4 c1 = *(const floatx4*)(Cl + (b + 1) * PP);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) a[kk] = aok ? Vb[4 * kk + lane / 16] : 0.f;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        acc = mfma16(a[kk], s_C[b * PP + (4 * kk + lane / 16) * P + lane % 16], acc);
+      for (int kk = 0; kk < 4; ++kk) {
+        acc = mfma16(a0[kk], c0[kk], acc);
+        acc1 = mfma16(a1[kk], c1[kk], acc1);
+      }
     }
+    if (b < nblk) {
+      const floatx4 a0 = aok ? *(const floatx4*)(Vr + (size_t)b * vstride) : floatx4{0.f, 0.f, 0.f, 0.f};
+      const floatx4 c0 = *(const floatx4*)(Cl + b * PP);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mfma16(a0[kk], c0[kk], acc);
+    }
+    acc += acc1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int row = r0 + 4 * (lane / 16) + q;
@@ -305,32 +328,55 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
 // ---------------------------------------------------------------------------
 // Small per-system dense steps (float64)
 // ---------------------------------------------------------------------------
-// Columns of W that (nearly) depend on earlier ones, from G = W^T W (the
-// Cholesky factorisation that skips a column whose pivot is <= tau G_cc).
-__global__ void bdep_kernel(int nsys, const BState* __restrict__ st, const double* __restrict__ Gd,
-                            size_t gstride, int* depmask, double tau) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsys || !running(st[s])) return;
-  const double* G = Gd + (size_t)s * gstride;
-  double R[PP];
-  for (int e = 0; e < PP; ++e) R[e] = 0.0;
+// Cholesky factorisation G = R^T R (R upper) of a 16 x 16 Gram matrix held in
+// LDS, one thread per entry (thread e owns row e / 16, column e % 16).
+// Right-looking: after step k the trailing entries hold
+// G_iq - sum_{k' <= k} R_k'i R_k'q, subtracted in the order of k, the same order
+// as the column-by-column form.  A pivot <= tau G_cc (G_cc the original
+// diagonal entry), or a non-finite one, skips column c: row c of R stays
+// zero.  Returns the mask of skipped columns (the same in every thread).
+// All 256 threads of the block must call it.
+__device__ int chol16_lds(double* sG, const double* gdiag, double* sR, double tau) {
+  const int i = threadIdx.x / P;
+  const int q = threadIdx.x % P;
+  sR[threadIdx.x] = 0.0;
+  __syncthreads();
   int mask = 0;
   for (int c = 0; c < P; ++c) {
-    double d = G[c * P + c];
-    for (int k = 0; k < c; ++k) d -= R[k * P + c] * R[k * P + c];
-    if (!(d > tau * G[c * P + c])) {
+    const double d = sG[c * P + c];
+    if (!(d > tau * gdiag[c]) || !isfinite(d)) {  // uniform over the block
       mask |= 1 << c;
       continue;
     }
     const double rcc = sqrt(d);
-    R[c * P + c] = rcc;
-    for (int q = c + 1; q < P; ++q) {
-      double v = G[c * P + q];
-      for (int k = 0; k < c; ++k) v -= R[k * P + c] * R[k * P + q];
-      R[c * P + q] = v / rcc;
-    }
+    if (i == c && q >= c) sR[c * P + q] = (q == c) ? rcc : sG[c * P + q] / rcc;
+    __syncthreads();
+    if (i > c && q >= i) sG[i * P + q] -= sR[c * P + i] * sR[c * P + q];
+    __syncthreads();
   }
-  depmask[s] = mask;
+  return mask;
+}
+
+// Loads the Gram matrix of system s into LDS (and its diagonal).
+__device__ void load_gram(const double* __restrict__ G, double* sG, double* gdiag) {
+  const double v = G[threadIdx.x];
+  sG[threadIdx.x] = v;
+  if (threadIdx.x / P == threadIdx.x % P) gdiag[threadIdx.x / P] = v;
+  __syncthreads();
+}
+
+// Columns of W that (nearly) depend on earlier ones, from G = W^T W (the
+// Cholesky factorisation that skips a column whose pivot is <= tau G_cc).
+// One block of 256 threads per system.
+__global__ __launch_bounds__(kBlock) void bdep_kernel(const BState* __restrict__ st,
+                                                      const double* __restrict__ Gd, size_t gstride,
+                                                      int* depmask, double tau) {
+  const int s = blockIdx.x;
+  if (!running(st[s])) return;
+  __shared__ double sG[PP], sR[PP], gdiag[P];
+  load_gram(Gd + (size_t)s * gstride, sG, gdiag);
+  const int mask = chol16_lds(sG, gdiag, sR, tau);
+  if (threadIdx.x == 0) depmask[s] = mask;
 }
 
 // T = W with the flagged columns taken from the random block Z.
@@ -360,71 +406,57 @@ __global__ __launch_bounds__(kBlock) void breplace_kernel(const BTile* __restric
 //   kCholPass2: breakdown in the second pass; Rbrk receives Rprev.
 enum { kCholStart = 0, kCholPass1 = 1, kCholPass2 = 2 };
 
-__global__ void bchol_kernel(int nsys, BState* st, const double* __restrict__ Gd, size_t gstride,
-                             const double* __restrict__ Rprev, double* __restrict__ Rout,
-                             float* __restrict__ Rinv_f, size_t rstride, double tau, int mode,
-                             double* __restrict__ Rbrk) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsys || !running(st[s])) return;
-  const double* G = Gd + (size_t)s * gstride;
-  double R[PP], Ri[PP];
-  for (int e = 0; e < PP; ++e) R[e] = Ri[e] = 0.0;
-  bool ok = true;
-  for (int c = 0; c < P; ++c) {
-    double d = G[c * P + c];
-    for (int k = 0; k < c; ++k) d -= R[k * P + c] * R[k * P + c];
-    if (!(d > tau * G[c * P + c]) || !isfinite(d)) {
-      ok = false;
-      continue;  // skip the column (zero row of R)
-    }
-    const double rcc = sqrt(d);
-    R[c * P + c] = rcc;
-    for (int q = c + 1; q < P; ++q) {
-      double v = G[c * P + q];
-      for (int k = 0; k < c; ++k) v -= R[k * P + c] * R[k * P + q];
-      R[c * P + q] = v / rcc;
-    }
-  }
-  if (!ok) {
+__global__ __launch_bounds__(kBlock) void bchol_kernel(BState* st, const double* __restrict__ Gd,
+                                                       size_t gstride, const double* __restrict__ Rprev,
+                                                       double* __restrict__ Rout, float* __restrict__ Rinv_f,
+                                                       size_t rstride, double tau, int mode,
+                                                       double* __restrict__ Rbrk) {
+  const int s = blockIdx.x;
+  if (!running(st[s])) return;
+  __shared__ double sG[PP], sR[PP], sRi[PP], gdiag[P];
+  load_gram(Gd + (size_t)s * gstride, sG, gdiag);
+  const int mask = chol16_lds(sG, gdiag, sR, tau);
+  const int e = threadIdx.x;
+  const int i = e / P;
+  const int c = e % P;
+  if (mask) {
     if (mode == kCholStart) {
-      st[s].cycle_done = 1;
-      st[s].failed = 1;
+      if (e == 0) {
+        st[s].cycle_done = 1;
+        st[s].failed = 1;
+      }
     } else {
       double* Rb = Rbrk + (size_t)s * PP;
-      if (mode == kCholPass1) {
-        for (int e = 0; e < PP; ++e) Rb[e] = isfinite(R[e]) ? R[e] : 0.0;
-      } else {
-        const double* Rp = Rprev + (size_t)s * PP;
-        for (int e = 0; e < PP; ++e) Rb[e] = Rp[e];
-      }
-      st[s].brk = 1;
+      Rb[e] = (mode == kCholPass1) ? (isfinite(sR[e]) ? sR[e] : 0.0) : Rprev[(size_t)s * PP + e];
+      if (e == 0) st[s].brk = 1;
     }
     return;
   }
-  // upper-triangular inverse, column by column
-  for (int c = 0; c < P; ++c) {
-    Ri[c * P + c] = 1.0 / R[c * P + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double v = 0.0;
-      for (int k = i + 1; k <= c; ++k) v += R[i * P + k] * Ri[k * P + c];
-      Ri[i * P + c] = -v / R[i * P + i];
+  // upper-triangular inverse, one row per step from the bottom:
+  // Ri[r][c] = -(sum_{k=r+1..c} R[r][k] Ri[k][c]) / R[r][r], Ri[r][r] = 1 / R[r][r]
+  sRi[e] = 0.0;
+  __syncthreads();
+  for (int r = P - 1; r >= 0; --r) {
+    if (i == r && c >= r) {
+      if (c == r) {
+        sRi[e] = 1.0 / sR[r * P + r];
+      } else {
+        double v = 0.0;
+        for (int k = r + 1; k <= c; ++k) v += sR[r * P + k] * sRi[k * P + c];
+        sRi[e] = -v / sR[r * P + r];
+      }
     }
+    __syncthreads();
   }
-  float* Rf = Rinv_f + (size_t)s * rstride;
-  for (int e = 0; e < PP; ++e) Rf[e] = float(Ri[e]);
+  Rinv_f[(size_t)s * rstride + e] = float(sRi[e]);
   if (Rout) {
-    double* Ro = Rout + (size_t)s * PP;
-    if (Rprev) {
+    double v = sR[e];
+    if (Rprev) {  // the two Cholesky QR passes combined: Rout = R Rprev
       const double* Rp = Rprev + (size_t)s * PP;
-      for (int i = 0; i < P; ++i)
-        for (int c = 0; c < P; ++c) {
-          double v = 0.0;
-          for (int k = i; k <= c; ++k) v += R[i * P + k] * Rp[k * P + c];
-          Ro[i * P + c] = v;
-        }
-    } else {
-      for (int e = 0; e < PP; ++e) Ro[e] = R[e];
+      v = 0.0;
+      for (int k = i; k <= c; ++k) v += sR[i * P + k] * Rp[k * P + c];
     }
+    Rout[(size_t)s * PP + e] = v;
   }
 }
 
@@ -450,9 +482,13 @@ __global__ __launch_bounds__(kBlock) void binit_rhs_kernel(const BState* __restr
 
 // One block column of the block Hessenberg matrix, [C1 + C2; R], reduced by the
 // earlier block Householder reflectors, then a new set of 16 reflectors on its
-// 32 x 16 panel; the same reflectors are applied to Grhs.  Lane c of the
-// single wave owns column c.  Reflector t of block column i acts on rows
-// 16 i + t .. 16 i + 31 and is stored as v (v_t = 1) with its tau.
+// 32 x 16 panel; the same reflectors are applied to Grhs.  Lane c < 16 of the
+// single wave owns column c and keeps a 32-row window of it in registers: the
+// reflectors of block column bi act on rows 16 bi .. 16 bi + 31 only, so after
+// block column bi the top 16 rows of the window are final and the window
+// slides down by 16 rows.  After the last earlier block column the window is
+// the new panel.  Reflector t of block column i acts on rows 16 i + t ..
+// 16 i + 31 and is stored as v (v_t = 1) with its tau.
 __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const double* __restrict__ C1d,
                                                     const double* __restrict__ C2d, size_t cstride,
                                                     const double* __restrict__ Rn, double* Hq,
@@ -461,85 +497,126 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
                                                     size_t gstride) {
   const int s = blockIdx.x;
   if (!st[s].active || st[s].cycle_done) return;  // a block column that broke down is kept
+  __shared__ double s_V[32 * P];
+  __shared__ double s_tau[P];
   __shared__ double s_v[32];
-  __shared__ double s_tau;
+  __shared__ double s_t;
   const int c = threadIdx.x;
+  const bool own = c < P;
+  const int cc = own ? c : 0;  // the other lanes shadow column 0 and write nothing
   double* H = Hq + (size_t)s * hstride;
   double* RF = refl + (size_t)s * rfstride * 32;   // [blockcol][32 rows][16 refl]
   double* TU = tauv + (size_t)s * rfstride;       // [blockcol][16]
   double* G = Grhs + (size_t)s * gstride;          // [row][16]
-  double* hc = H + (size_t)(16 * j + (c < P ? c : 0)) * ldh;
-  if (c < P) {
-    for (int b = 0; b <= j; ++b)
-      for (int i = 0; i < P; ++i) {
-        const size_t e = (size_t)s * cstride + (size_t)b * PP + i * P + c;
-        hc[16 * b + i] = C1d[e] + C2d[e];
-      }
-    for (int i = 0; i < P; ++i) hc[16 * (j + 1) + i] = Rn[(size_t)s * PP + i * P + c];
-    for (int i = 16 * (j + 2); i < ldh; ++i) hc[i] = 0.0;
-    // earlier reflectors
-    for (int bi = 0; bi < j; ++bi) {
-      const double* V = RF + (size_t)bi * 32 * P;
-      for (int t = 0; t < P; ++t) {
-        const double tau = TU[bi * P + t];
-        if (tau == 0.0) continue;
-        double dot = hc[16 * bi + t];
-        for (int r = t + 1; r < 32; ++r) dot += V[r * P + t] * hc[16 * bi + r];
-        dot *= tau;
-        hc[16 * bi + t] -= dot;
-        for (int r = t + 1; r < 32; ++r) hc[16 * bi + r] -= dot * V[r * P + t];
-      }
+  double* hcol = H + (size_t)(16 * j + cc) * ldh;
+  const double* C1 = C1d + (size_t)s * cstride;
+  const double* C2 = C2d + (size_t)s * cstride;
+  const double* Rs = Rn + (size_t)s * PP;
+  // entry of the new column in row 16 b + i
+  auto entry = [&](int b, int i) -> double {
+    if (b <= j) return C1[b * PP + i * P + cc] + C2[b * PP + i * P + cc];
+    if (b == j + 1) return Rs[i * P + cc];
+    return 0.0;
+  };
+  double w[32];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    w[i] = entry(0, i);
+    w[P + i] = entry(1, i);
+  }
+  // earlier reflectors
+  for (int bi = 0; bi < j; ++bi) {
+    for (int e = threadIdx.x; e < 32 * P; e += kWave) s_V[e] = RF[(size_t)bi * 32 * P + e];
+    if (threadIdx.x < P) s_tau[threadIdx.x] = TU[bi * P + threadIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+      const double tau = s_tau[t];
+      if (tau == 0.0) continue;
+      double dot = w[t];
+#pragma unroll
+      for (int r = t + 1; r < 32; ++r) dot += s_V[r * P + t] * w[r];
+      dot *= tau;
+      w[t] -= dot;
+#pragma unroll
+      for (int r = t + 1; r < 32; ++r) w[r] -= dot * s_V[r * P + t];
+    }
+    __syncthreads();  // s_V is overwritten next
+    if (own) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) hcol[16 * bi + i] = w[i];
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      w[i] = w[P + i];
+      w[P + i] = entry(bi + 2, i);
     }
   }
-  __syncthreads();
   // new reflectors on the panel rows 16 j .. 16 j + 31
+  double g[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) g[r] = G[(size_t)(16 * j + r) * P + cc];
   double* Vn = RF + (size_t)j * 32 * P;
+#pragma unroll
   for (int t = 0; t < P; ++t) {
     if (c == t) {
-      const double alpha = hc[16 * j + t];
+      const double alpha = w[t];
       double xn2 = 0.0;
-      for (int r = t + 1; r < 32; ++r) xn2 += hc[16 * j + r] * hc[16 * j + r];
+#pragma unroll
+      for (int r = t + 1; r < 32; ++r) xn2 += w[r] * w[r];
       double tau = 0.0;
       double beta = alpha;
       if (xn2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
         tau = (beta - alpha) / beta;
         const double sc = 1.0 / (alpha - beta);
+#pragma unroll
         for (int r = t + 1; r < 32; ++r) {
-          const double v = hc[16 * j + r] * sc;
+          const double v = w[r] * sc;
           s_v[r] = v;
           Vn[r * P + t] = v;
-          hc[16 * j + r] = 0.0;
+          w[r] = 0.0;
         }
       } else {
+#pragma unroll
         for (int r = t + 1; r < 32; ++r) {
           s_v[r] = 0.0;
           Vn[r * P + t] = 0.0;
         }
       }
-      hc[16 * j + t] = beta;
-      s_tau = tau;
+      w[t] = beta;
+      s_t = tau;
       TU[j * P + t] = tau;
     }
     __syncthreads();
-    const double tau = s_tau;
-    if (tau != 0.0) {
-      if (c > t && c < P) {
-        double dot = hc[16 * j + t];
-        for (int r = t + 1; r < 32; ++r) dot += s_v[r] * hc[16 * j + r];
+    const double tau = s_t;
+    if (tau != 0.0 && own) {
+      if (c > t) {
+        double dot = w[t];
+#pragma unroll
+        for (int r = t + 1; r < 32; ++r) dot += s_v[r] * w[r];
         dot *= tau;
-        hc[16 * j + t] -= dot;
-        for (int r = t + 1; r < 32; ++r) hc[16 * j + r] -= dot * s_v[r];
+        w[t] -= dot;
+#pragma unroll
+        for (int r = t + 1; r < 32; ++r) w[r] -= dot * s_v[r];
       }
-      if (c < P) {
-        double dot = G[(size_t)(16 * j + t) * P + c];
-        for (int r = t + 1; r < 32; ++r) dot += s_v[r] * G[(size_t)(16 * j + r) * P + c];
-        dot *= tau;
-        G[(size_t)(16 * j + t) * P + c] -= dot;
-        for (int r = t + 1; r < 32; ++r) G[(size_t)(16 * j + r) * P + c] -= dot * s_v[r];
-      }
+      double dot = g[t];
+#pragma unroll
+      for (int r = t + 1; r < 32; ++r) dot += s_v[r] * g[r];
+      dot *= tau;
+      g[t] -= dot;
+#pragma unroll
+      for (int r = t + 1; r < 32; ++r) g[r] -= dot * s_v[r];
     }
     __syncthreads();
+  }
+  if (own) {
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      hcol[16 * j + r] = w[r];
+      G[(size_t)(16 * j + r) * P + c] = g[r];
+    }
+    for (int i = 16 * (j + 2); i < ldh; ++i) hcol[i] = 0.0;
   }
   if (c == 0) {
     st[s].kblk = j + 1;
@@ -730,7 +807,7 @@ gmr_status gemm(const BRun& R, const float* V, int nblk, const float* Cf, float*
 
 gmr_status chol(const BRun& R, const double* Gd, const double* Rprev, double* Rout, double tau, int mode) {
   const int ns = R.b->nsys;
-  bchol_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, R.at<BState>(R.L.st), Gd, R.L.cstride, Rprev, Rout,
+  bchol_kernel<<<ns, kBlock, 0, R.s>>>(R.at<BState>(R.L.st), Gd, R.L.cstride, Rprev, Rout,
                                                R.at<float>(R.L.Cf), R.L.cstride, tau, mode,
                                                R.at<double>(R.L.Rn));
   return launch_check("bchol_kernel");
@@ -901,7 +978,8 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
     bstart_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, R64, gam, W);
     BT(launch_check("bstart_kernel"));
     BT(dots(R, W, 1, W, Cd, nullptr));
-    bdep_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, st, Cd, R.L.cstride, R.at<int>(R.L.dep), 1e-5);
+    bdep_kernel<<<ns, kBlock, 0, R.s>>>(st, Cd, R.L.cstride, R.at<int>(R.L.dep), 1e-5);
+    BT(launch_check("bdep_kernel"));
     breplace_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, R.at<int>(R.L.dep), W, Z, T);
     BT(launch_check("breplace_kernel"));
     BT(cholqr2(R, T, V, 1e-12, true));
@@ -993,7 +1071,7 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
         if ((status = gemm<kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))) != GMR_OK) break;
         if (hipEventRecord(e1, R.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { status = GMR_ERR_HIP; break; }
         float t = 0.f;
-        hipEventElapsedTime(&t, e0, e1);
+        (void)hipEventElapsedTime(&t, e0, e1);
         if (rep > 0) ms += t;
       }
       if (status != GMR_OK) break;
@@ -1005,8 +1083,8 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
     }
     if (status != GMR_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   build_tiles(b, bt);
   b->gb = bg;
   if (status != GMR_OK) return gmr::fail(status, "batch_autotune: a timed launch failed");
