@@ -243,6 +243,17 @@ def batch(args):
     t = time.perf_counter() - t0
     assert out["status"] == 0, out["status_name"]
     Xh = X.cpu().numpy()
+    del ws
+    log(f"bench: batched GMRES-IR {t:.2f} s; float64 batched block GMRES")
+    ws64 = G.alloc_workspace(bt.workspace_bytes(G.GMR_F64), dev)
+    X64 = torch.zeros_like(Bd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out64 = bt.solve(A64, None, Bd, X64, Zd, ws64, tol=1e-10, max_cycles=500)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    assert out64["status"] == 0, out64["status_name"]
+    del ws64
     offs = np.concatenate([[0], np.cumsum([s["A"].n for s in systems])])
     worst = 0.0
     for s in range(0, len(systems), 17):
@@ -258,7 +269,10 @@ def batch(args):
                        "systems": len(systems), "rhs": 16, "rows": A.n, "nnz": A.nnz, "restart": m},
             "rhs_solved_per_s": round(len(systems) * 16 / t, 2), "tiling": list(tiling[:2]),
             "cycles_slowest_system": out["cycles"], "block_iters": out["block_iters"],
-            "max_rel_res": out["max_rel_res"], "sampled_host_rel_res": worst}
+            "max_rel_res": out["max_rel_res"], "sampled_host_rel_res": worst,
+            "fp64_batched_s": round(t64, 4), "ir_speedup_vs_fp64": round(t64 / t, 3),
+            "fp64_cycles_slowest_system": out64["cycles"], "fp64_block_iters": out64["block_iters"],
+            "fp64_max_rel_res": out64["max_rel_res"]}
 
 
 def predictor(args):

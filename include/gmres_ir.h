@@ -194,10 +194,11 @@ gmr_status gmr_leja_order(int32_t k, double* re, double* im);
  * each (the paper's solver handles one right-hand side, §IV; this is the
  * multi-system, multi-RHS growth of the same method).  Per system, the 16
  * right-hand sides share one block Krylov space built with two block
- * classical Gram-Schmidt passes (block CGS2, §III-A) on the FP32 matrix cores
+ * classical Gram-Schmidt passes (block CGS2, §III-A) on the matrix cores
  * and Cholesky QR twice inside each block; the outer loop is GMRES-IR
  * (Alg. 2) with float64 residuals and updates, each column scaled by its own
- * residual norm.
+ * residual norm.  The inner solve runs in float32 (batch_gmres_ir_solve) or,
+ * as the baseline, in float64 (batch_gmres_solve).
  * ------------------------------------------------------------------------- */
 typedef struct gmr_batch gmr_batch;  /* opaque, host-side: sizes and the tile table */
 
@@ -217,8 +218,10 @@ gmr_status batch_create(int32_t nsys, const int32_t* sys_rows, int32_t nrhs, int
                         gmr_batch** out);
 void batch_destroy(gmr_batch* b);
 
-/* Device workspace needed by batch_gmres_ir_solve, batch_autotune and batch_bcgs_step. */
-size_t batch_workspace_bytes(const gmr_batch* b);
+/* Device workspace needed with inner precision inner_dtype: GMR_F32 for
+ * batch_gmres_ir_solve, batch_autotune and batch_bcgs_step, GMR_F64 for
+ * batch_gmres_solve.  0 for a null batch or another dtype. */
+size_t batch_workspace_bytes(const gmr_batch* b, int32_t inner_dtype);
 
 /* Tiling of the matrix-core kernels: rows per tile (multiple of 16, >= 256) and
  * basis blocks accumulated per pass (4, 8 or 16). */
@@ -241,6 +244,15 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
                                 double* X, const float* Z, double tol, int32_t max_cycles, void* ws,
                                 size_t ws_bytes, gmr_batch_result* res, int32_t* sys_cycles,
                                 double* sys_rel_res, void* stream);
+
+/* The same solve with the whole inner block GMRES(m) in float64 (block
+ * Gram-Schmidt on the float64 matrix cores): plain restarted block GMRES, the
+ * reference the mixed-precision solve is measured against (§V-B's comparison
+ * for the batched case).  Arguments as batch_gmres_ir_solve, with no float32
+ * matrix; the workspace is batch_workspace_bytes(b, GMR_F64).  Synchronous. */
+gmr_status batch_gmres_solve(gmr_batch* b, const gmr_csr* A64, const double* B, double* X, const float* Z,
+                             double tol, int32_t max_cycles, void* ws, size_t ws_bytes, gmr_batch_result* res,
+                             int32_t* sys_cycles, double* sys_rel_res, void* stream);
 
 /* One block Gram-Schmidt pass on its own (for tests): C = V^T W per system
  * (device float64 out, nsys x nblk x 16 x 16, C[s][b][i][c]) and W -= V C.

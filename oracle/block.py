@@ -12,7 +12,8 @@ block Hessenberg least-squares problem min ||E1 R0 - Hbar Y||_F is solved
 column by column with numpy's lstsq.  GMRES-IR (Alg. 2) wraps it: the inner
 block GMRES runs in float32 on float32 A for exactly m block steps, the
 residual and the update are float64, and every right-hand side column is
-scaled by its own residual norm before the cast.
+scaled by its own residual norm before the cast.  With a float64 inner solve
+the same loop is plain restarted block GMRES(m).
 """
 from __future__ import annotations
 
@@ -133,11 +134,13 @@ class BlockOutcome:
 
 
 def block_gmres_ir(A, B: np.ndarray, m: int, tol: float, max_cycles: int,
-                   Z: np.ndarray = None) -> BlockOutcome:
+                   Z: np.ndarray = None, inner=np.float32) -> BlockOutcome:
     """Block GMRES(m)-IR: float32 inner block GMRES(m), float64 outer refinement.
-    Z (n x p) is the random block that replaces dependent start columns."""
+    Z (n x p) is the random block that replaces dependent start columns.
+    inner=np.float64 runs the same loop with the inner block GMRES in float64,
+    i.e. plain restarted block GMRES(m) in float64 (the baseline of §V-B)."""
     n, p = B.shape
-    f32 = np.float32
+    f32 = inner
     if Z is None:
         Z = np.random.default_rng(0).uniform(-1, 1, (n, p))
     X = np.zeros((n, p))

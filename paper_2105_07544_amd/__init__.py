@@ -304,8 +304,10 @@ class Batch:
     def handle(self):
         return self._h
 
-    def workspace_bytes(self) -> int:
-        return int(lib().batch_workspace_bytes(self._h))
+    def workspace_bytes(self, inner: int = GMR_F32) -> int:
+        """Workspace of the float32-inner solve (and autotune, bcgs_step), or of
+        the float64 one with inner=GMR_F64."""
+        return int(lib().batch_workspace_bytes(self._h, int(inner)))
 
     def set_tiling(self, tile_rows: int, group_blocks: int):
         check(lib().batch_set_tiling(self._h, tile_rows, group_blocks))
@@ -321,16 +323,24 @@ class Batch:
                                    _stream(ws.device)))
         return t.value, g.value, ms.value
 
-    def solve(self, A64: DeviceCSR, A32: DeviceCSR, B: torch.Tensor, X: torch.Tensor, Z: torch.Tensor,
-              ws: torch.Tensor, tol: float = 1e-10, max_cycles: int = 100):
+    def solve(self, A64: DeviceCSR, A32: Optional[DeviceCSR], B: torch.Tensor, X: torch.Tensor,
+              Z: torch.Tensor, ws: torch.Tensor, tol: float = 1e-10, max_cycles: int = 100):
+        """GMRES-IR with the float32 inner solve on A32, or, with A32=None, plain
+        float64 block GMRES (workspace_bytes(GMR_F64))."""
         res = _capi.gmr_batch_result()
         cyc = np.zeros(self.nsys, dtype=np.int32)
         rel = np.zeros(self.nsys * 16)
-        s64, s32 = A64.struct(), A32.struct()
-        status = lib().batch_gmres_ir_solve(self._h, C.byref(s64), C.byref(s32), _ptr(B), _ptr(X), _ptr(Z),
-                                            float(tol), int(max_cycles), _ptr(ws), ws.numel(), C.byref(res),
-                                            cyc.ctypes.data_as(C.c_void_p), rel.ctypes.data_as(C.c_void_p),
-                                            _stream(B.device))
+        s64 = A64.struct()
+        cp, rp = cyc.ctypes.data_as(C.c_void_p), rel.ctypes.data_as(C.c_void_p)
+        if A32 is None:
+            status = lib().batch_gmres_solve(self._h, C.byref(s64), _ptr(B), _ptr(X), _ptr(Z), float(tol),
+                                             int(max_cycles), _ptr(ws), ws.numel(), C.byref(res), cp, rp,
+                                             _stream(B.device))
+        else:
+            s32 = A32.struct()
+            status = lib().batch_gmres_ir_solve(self._h, C.byref(s64), C.byref(s32), _ptr(B), _ptr(X), _ptr(Z),
+                                                float(tol), int(max_cycles), _ptr(ws), ws.numel(), C.byref(res),
+                                                cp, rp, _stream(B.device))
         check(status)
         return {"status": res.status, "status_name": _capi.STATUS.get(res.status, str(res.status)),
                 "cycles": res.cycles, "block_iters": res.block_iters, "max_rel_res": res.max_rel_res,

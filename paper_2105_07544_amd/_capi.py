@@ -23,7 +23,7 @@ EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "po
             "poly_prec_destroy", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
             "gmres_ir_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
-            "batch_set_tiling", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve",
+            "batch_set_tiling", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve", "batch_gmres_solve",
             "batch_bcgs_step", "mlp_param_count", "mlp_workspace_bytes", "mlp_forward",
             "mlp_loss_grad", "mlp_adam_step", "matrix_stats"]
 
@@ -101,7 +101,7 @@ def load() -> C.CDLL:
     lib.batch_create.restype = st
     lib.batch_destroy.argtypes = [P]
     lib.batch_destroy.restype = None
-    lib.batch_workspace_bytes.argtypes = [P]
+    lib.batch_workspace_bytes.argtypes = [P, C.c_int32]
     lib.batch_workspace_bytes.restype = C.c_size_t
     lib.batch_set_tiling.argtypes = [P, C.c_int32, C.c_int32]
     lib.batch_set_tiling.restype = st
@@ -113,6 +113,9 @@ def load() -> C.CDLL:
     lib.batch_gmres_ir_solve.argtypes = [P, C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P, C.c_double,
                                          C.c_int32, P, C.c_size_t, C.POINTER(gmr_batch_result), P, P, P]
     lib.batch_gmres_ir_solve.restype = st
+    lib.batch_gmres_solve.argtypes = [P, C.POINTER(gmr_csr), P, P, P, C.c_double, C.c_int32, P, C.c_size_t,
+                                      C.POINTER(gmr_batch_result), P, P, P]
+    lib.batch_gmres_solve.restype = st
     lib.batch_bcgs_step.argtypes = [P, P, C.c_int32, P, P, P, C.c_size_t, P]
     lib.batch_bcgs_step.restype = st
     lib.mlp_param_count.argtypes = []

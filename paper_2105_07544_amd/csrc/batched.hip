@@ -7,11 +7,14 @@
 // Gram-Schmidt passes (the block form of the CGS2 of §III-A) and within itself
 // by Cholesky QR done twice.  The block Gram-Schmidt products V^T W and V C
 // are dense contractions of shape (16 j x rows) x (rows x 16) and
-// (rows x 16 j) x (16 j x 16); they run on the FP32 matrix cores
-// (v_mfma_f32_16x16x4f32) with FP32 accumulation.  The outer loop is GMRES-IR
+// (rows x 16 j) x (16 j x 16); they run on the matrix cores
+// (v_mfma_f32_16x16x4f32 with FP32 accumulation for the float32 inner solve,
+// v_mfma_f64_16x16x4f64 for the float64 one).  The outer loop is GMRES-IR
 // (Alg. 2) per system: float64 block residual B - A X, every column scaled by
-// its own residual norm, float64 update of X.  The block least-squares
-// problem is solved per system in float64 with block Householder reflectors.
+// its own residual norm, float64 update of X.  With a float64 inner solve the
+// same loop is plain restarted block GMRES(m) in float64, the baseline the
+// mixed-precision solve is compared with.  The block least-squares problem is
+// solved per system in float64 with block Householder reflectors.
 //
 // Work is described by a tile table: every system's rows are cut into tiles
 // of at most `tile_rows` rows; a kernel launch covers all tiles of all
@@ -37,6 +40,27 @@ constexpr int P = 16;          // right-hand sides per system = block size
 constexpr int PP = P * P;      // entries of a 16 x 16 block
 constexpr int kMaxBlocks = 65; // restart m <= 64 block steps
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// The 16x16x4 matrix-core step for the inner precision T.  Operand A: lane l
+// holds A[l%16][l/16]; operand B: lane l holds B[l/16][l%16]; element q of the
+// result in lane l is D[row(l/16, q)][l%16] (the two instructions order the
+// result rows differently).
+template <class T> struct Mx;
+template <> struct Mx<float> {
+  typedef floatx4 v4;
+  static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int q) { return 4 * g + q; }
+};
+template <> struct Mx<double> {
+  typedef doublex4 v4;
+  static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int q) { return 4 * q + g; }
+};
 
 struct BTile { int sys, r0, nr, pad; };
 struct BSys { int row_off, n, tile_start, tile_count; };
@@ -52,31 +76,68 @@ struct BState {
 // A system whose block step is in progress.
 __device__ __forceinline__ bool running(const BState& s) { return s.active && !s.cycle_done && !s.brk; }
 
-__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
 // ---------------------------------------------------------------------------
-// SpMM (float32 inner): Y = A X for the tiles of running systems.  16 lanes per
+// SpMM in the inner precision: Y = A X for the tiles of running systems.  16 lanes per
 // row (one per right-hand side), 16 rows per block pass, nonzeros in ascending k.
 // ---------------------------------------------------------------------------
+template <class T>
 __global__ __launch_bounds__(kBlock) void bspmm_kernel(const BTile* __restrict__ tiles,
                                                        const BState* __restrict__ st,
                                                        const int* __restrict__ rp,
                                                        const int* __restrict__ ci,
-                                                       const float* __restrict__ val,
-                                                       const float* __restrict__ X,
-                                                       float* __restrict__ Y) {
+                                                       const T* __restrict__ val,
+                                                       const T* __restrict__ X,
+                                                       T* __restrict__ Y) {
   const BTile tl = tiles[blockIdx.x];
   if (!running(st[tl.sys])) return;
   const int c = threadIdx.x % P;
   const int rs = threadIdx.x / P;
   const int rend = tl.r0 + tl.nr;
-  for (int r = tl.r0 + rs; r < rend; r += kBlock / P) {
-    float acc = 0.f;
-    const int k1 = rp[r + 1];
-    for (int k = rp[r]; k < k1; ++k) acc += val[k] * X[(size_t)ci[k] * P + c];
-    Y[(size_t)r * P + c] = acc;
+  // RU rows per thread at a time and KU nonzeros per row at a time, so that the
+  // dependent loads (row pointers, then indices and values, then X) of several
+  // rows overlap; every row is still summed in ascending k.
+  constexpr int RU = 4, KU = 8, RS = kBlock / P;
+  for (int r = tl.r0 + rs; r < rend; r += RU * RS) {
+    int k0[RU], k1[RU];
+    int kmax = 0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int rr = r + u * RS;
+      k0[u] = rr < rend ? rp[rr] : 0;
+      k1[u] = rr < rend ? rp[rr + 1] : 0;
+      kmax = max(kmax, k1[u] - k0[u]);
+    }
+    T acc[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) acc[u] = T(0);
+    for (int o = 0; o < kmax; o += KU) {
+      int cx[RU][KU];
+      T a[RU][KU], xv[RU][KU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int t = 0; t < KU; ++t) {
+          const int k = k0[u] + o + t;
+          const bool in = k < k1[u];
+          cx[u][t] = in ? ci[k] : 0;
+          a[u][t] = in ? val[k] : T(0);
+        }
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int t = 0; t < KU; ++t)
+          xv[u][t] = (k0[u] + o + t < k1[u]) ? X[(size_t)cx[u][t] * P + c] : T(0);
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int t = 0; t < KU; ++t)
+          if (k0[u] + o + t < k1[u]) acc[u] += a[u][t] * xv[u][t];
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int rr = r + u * RS;
+      if (rr < rend) Y[(size_t)rr * P + c] = acc[u];
+    }
   }
 }
 
@@ -145,19 +206,20 @@ __global__ void bfinish_res_kernel(int nsys, const BSys* __restrict__ sys, BStat
   if (mode == 1 && threadIdx.x == 0) st[s].active = s_any;
 }
 
-// Start of a cycle: W = float(R / gamma_c) per column (0 for a column with gamma 0).
+// Start of a cycle: W = T(R / gamma_c) per column (0 for a column with gamma 0).
+template <class T>
 __global__ __launch_bounds__(kBlock) void bstart_kernel(const BTile* __restrict__ tiles,
                                                         const BState* __restrict__ st,
                                                         const double* __restrict__ R,
                                                         const double* __restrict__ gam,
-                                                        float* __restrict__ W) {
+                                                        T* __restrict__ W) {
   const BTile tl = tiles[blockIdx.x];
   if (!running(st[tl.sys])) return;
   const int c = threadIdx.x % P;
   const double g = gam[tl.sys * P + c];
   const double ig = g > 0.0 ? 1.0 / g : 0.0;
   for (int r = tl.r0 + (int)threadIdx.x / P; r < tl.r0 + tl.nr; r += kBlock / P)
-    W[(size_t)r * P + c] = float(R[(size_t)r * P + c] * ig);
+    W[(size_t)r * P + c] = T(R[(size_t)r * P + c] * ig);
 }
 
 // ---------------------------------------------------------------------------
@@ -169,15 +231,16 @@ __global__ __launch_bounds__(kBlock) void bstart_kernel(const BTile* __restrict_
 // load.  The row sum is the MFMA's K accumulation; GB blocks are accumulated
 // per pass over the rows.
 // ---------------------------------------------------------------------------
-template <int GB>
+template <class T, int GB>
 __global__ __launch_bounds__(kBlock) void bdots_kernel(const BTile* __restrict__ tiles,
                                                        const BState* __restrict__ st,
-                                                       const float* __restrict__ V,
+                                                       const T* __restrict__ V,
                                                        size_t vstride, int nblk,
-                                                       const float* __restrict__ W,
-                                                       float* __restrict__ partial,
+                                                       const T* __restrict__ W,
+                                                       T* __restrict__ partial,
                                                        size_t pstride) {
-  __shared__ float s_acc[kWavesPerBlock][GB][PP];
+  typedef typename Mx<T>::v4 v4;
+  __shared__ T s_acc[kWavesPerBlock][GB][PP];
   const BTile tl = tiles[blockIdx.x];
   if (!running(st[tl.sys])) return;
   const int lane = threadIdx.x % kWave;
@@ -186,29 +249,40 @@ __global__ __launch_bounds__(kBlock) void bdots_kernel(const BTile* __restrict__
   const int col = lane % P;
   const int rend = tl.r0 + tl.nr;
   for (int g0 = 0; g0 < nblk; g0 += GB) {
-    floatx4 acc[GB];
+    v4 acc[GB];
 #pragma unroll
-    for (int b = 0; b < GB; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int r = tl.r0 + 4 * wave; r < rend; r += 4 * kWavesPerBlock) {
-      const int row = r + rsub;
-      const bool ok = row < rend;
-      const float bw = ok ? W[(size_t)row * P + col] : 0.f;
-      float a[GB];
+    for (int b = 0; b < GB; ++b) acc[b] = v4{T(0), T(0), T(0), T(0)};
+    // two 4-row slices per iteration (rows r .. r+3 and r+4 .. r+7), so that
+    // 2 (GB + 1) loads are in flight per lane
+    for (int r = tl.r0 + 8 * wave; r < rend; r += 8 * kWavesPerBlock) {
+      const int row0 = r + rsub;
+      const int row1 = r + 4 + rsub;
+      const bool ok0 = row0 < rend;
+      const bool ok1 = row1 < rend;
+      const T bw0 = ok0 ? W[(size_t)row0 * P + col] : T(0);
+      const T bw1 = ok1 ? W[(size_t)row1 * P + col] : T(0);
+      T a0[GB], a1[GB];
+#pragma unroll
+      for (int b = 0; b < GB; ++b) {
+        const T* Vb = V + (size_t)(g0 + b) * vstride;
+        a0[b] = (ok0 && g0 + b < nblk) ? Vb[(size_t)row0 * P + col] : T(0);
+        a1[b] = (ok1 && g0 + b < nblk) ? Vb[(size_t)row1 * P + col] : T(0);
+      }
 #pragma unroll
       for (int b = 0; b < GB; ++b)
-        a[b] = (ok && g0 + b < nblk) ? V[(size_t)(g0 + b) * vstride + (size_t)row * P + col] : 0.f;
-#pragma unroll
-      for (int b = 0; b < GB; ++b)
-        if (g0 + b < nblk) acc[b] = mfma16(a[b], bw, acc[b]);
+        if (g0 + b < nblk) {
+          acc[b] = Mx<T>::mfma(a0[b], bw0, acc[b]);
+          acc[b] = Mx<T>::mfma(a1[b], bw1, acc[b]);
+        }
     }
 #pragma unroll
     for (int b = 0; b < GB; ++b)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s_acc[wave][b][(4 * rsub + q) * P + col] = acc[b][q];
+      for (int q = 0; q < 4; ++q) s_acc[wave][b][Mx<T>::row(rsub, q) * P + col] = acc[b][q];
     __syncthreads();
     for (int b = 0; b < GB && g0 + b < nblk; ++b) {
       const int e = threadIdx.x;
-      float sum = s_acc[0][b][e];
+      T sum = s_acc[0][b][e];
 #pragma unroll
       for (int w = 1; w < kWavesPerBlock; ++w) sum += s_acc[w][b][e];
       partial[(size_t)blockIdx.x * pstride + (size_t)(g0 + b) * PP + e] = sum;
@@ -219,10 +293,11 @@ __global__ __launch_bounds__(kBlock) void bdots_kernel(const BTile* __restrict__
 
 // Per system and block b: the tile partials added in tile order (float64),
 // stored as Cd[s][b][.] and rounded into Cf[s][b][.] (matrix-core operand).
+template <class T>
 __global__ __launch_bounds__(kBlock) void bfinish_c_kernel(const BSys* __restrict__ sys,
                                                            const BState* __restrict__ st,
-                                                           const float* __restrict__ partial,
-                                                           size_t pstride, double* Cd, float* Cf,
+                                                           const T* __restrict__ partial,
+                                                           size_t pstride, double* Cd, T* Cf,
                                                            size_t cstride) {
   const int s = blockIdx.x;
   const int b = blockIdx.y;
@@ -232,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void bfinish_c_kernel(const BSys* __restric
   for (int t = 0; t < sys[s].tile_count; ++t)
     sum += partial[(size_t)(sys[s].tile_start + t) * pstride + (size_t)b * PP + e];
   Cd[(size_t)s * cstride + (size_t)b * PP + e] = sum;
-  if (Cf) Cf[(size_t)s * cstride + (size_t)b * PP + e] = float(sum);
+  if (Cf) Cf[(size_t)s * cstride + (size_t)b * PP + e] = T(sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -245,19 +320,22 @@ __global__ __launch_bounds__(kBlock) void bfinish_c_kernel(const BSys* __restric
 // (the wave reads 16 whole rows, 1 KB contiguous) and feeds element kk to step
 // kk, whose B operand is C_b[4g + kk][l%16].  The coefficients sit in LDS as
 // s_C[b][g][c][kk], so the four B values of a lane are one 16-byte LDS read.
-// Result: lane l holds rows r0 + 4(l/16) + q, column l%16.
+// (float64: 32-byte loads and reads, same order.)  Result: lane l holds rows
+// r0 + Mx::row(l/16, q), column l%16.
 // ---------------------------------------------------------------------------
 enum { kSub = 0, kSet = 1, kXupd = 2 };
 
-template <int MODE>
+template <class T, int MODE>
 __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__ tiles,
                                                        const BState* __restrict__ st,
-                                                       const float* V, size_t vstride, int nblk_arg,
-                                                       const float* __restrict__ Cf, size_t cstride,
-                                                       float* out, double* __restrict__ X64,
+                                                       const T* V, size_t vstride, int nblk_arg,
+                                                       const T* __restrict__ Cf, size_t cstride,
+                                                       T* out, double* __restrict__ X64,
                                                        const double* __restrict__ gam,
                                                        const double* __restrict__ bnorm, double tol) {
-  extern __shared__ float s_C[];  // nblk x 16 x 16 coefficients (dynamic)
+  typedef typename Mx<T>::v4 v4;
+  extern __shared__ __align__(16) char s_dyn[];
+  T* s_C = reinterpret_cast<T*>(s_dyn);  // nblk x 16 x 16 coefficients (dynamic)
   const BTile tl = tiles[blockIdx.x];
   const BState ss = st[tl.sys];
   int nblk = nblk_arg;
@@ -267,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
   } else {
     if (!running(ss)) return;
   }
-  const float* C = Cf + (size_t)tl.sys * cstride;
+  const T* C = Cf + (size_t)tl.sys * cstride;
   for (int e = threadIdx.x; e < nblk * PP; e += kBlock) {
     const int b = e / PP, i = (e / P) % P, c = e % P;  // C_b[i][c], i = 4 g + kk
     s_C[((b * 4 + i / 4) * P + c) * 4 + i % 4] = C[e];
@@ -286,35 +364,40 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
   for (int r0 = tl.r0 + 16 * wave; r0 < rend; r0 += 16 * kWavesPerBlock) {
     const int arow = r0 + lane % 16;
     const bool aok = arow < rend;
-    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+    const v4 z = v4{T(0), T(0), T(0), T(0)};
+    v4 acc = z;
     const int g = lane / 16;
     // two accumulators (even and odd b) so that consecutive MFMAs are independent
-    floatx4 acc1 = floatx4{0.f, 0.f, 0.f, 0.f};
-    const float* Vr = V + (size_t)arow * P + 4 * g;
-    const float* Cl = s_C + (g * P + lane % 16) * 4;
+    v4 acc1 = z;
+    const T* Vr = V + (size_t)arow * P + 4 * g;
+    const T* Cl = s_C + (g * P + lane % 16) * 4;
+    // eight blocks per iteration: eight vector loads in flight per lane
     int b = 0;
-    for (; b + 1 < nblk; b += 2) {
-      const floatx4 z = floatx4{0.f, 0.f, 0.f, 0.f};
-      const floatx4 a0 = aok ? *(const floatx4*)(Vr + (size_t)b * vstride) : z;
-      const floatx4 a1 = aok ? *(const floatx4*)(Vr + (size_t)(b + 1) * vstride) : z;
-      const floatx4 c0 = *(const floatx4*)(Cl + b * PP);
-      const floatx4 c1 = *(const floatx4*)(Cl + (b + 1) * PP);
+    for (; b + 7 < nblk; b += 8) {
+      v4 a[8], cb[8];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        acc = mfma16(a0[kk], c0[kk], acc);
-        acc1 = mfma16(a1[kk], c1[kk], acc1);
+      for (int u = 0; u < 8; ++u) {
+        a[u] = aok ? *(const v4*)(Vr + (size_t)(b + u) * vstride) : z;
+        cb[u] = *(const v4*)(Cl + (b + u) * PP);
       }
-    }
-    if (b < nblk) {
-      const floatx4 a0 = aok ? *(const floatx4*)(Vr + (size_t)b * vstride) : floatx4{0.f, 0.f, 0.f, 0.f};
-      const floatx4 c0 = *(const floatx4*)(Cl + b * PP);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = mfma16(a0[kk], c0[kk], acc);
+      for (int u = 0; u < 8; u += 2)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          acc = Mx<T>::mfma(a[u][kk], cb[u][kk], acc);
+          acc1 = Mx<T>::mfma(a[u + 1][kk], cb[u + 1][kk], acc1);
+        }
+    }
+    for (; b < nblk; ++b) {
+      const v4 a0 = aok ? *(const v4*)(Vr + (size_t)b * vstride) : z;
+      const v4 c0 = *(const v4*)(Cl + b * PP);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = Mx<T>::mfma(a0[kk], c0[kk], acc);
     }
     acc += acc1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int row = r0 + 4 * (lane / 16) + q;
+      const int row = r0 + Mx<T>::row(lane / 16, q);
       if (row < rend) {
         const size_t idx = (size_t)row * P + lane % 16;
         if constexpr (MODE == kSub) out[idx] -= acc[q];
@@ -380,23 +463,24 @@ __global__ __launch_bounds__(kBlock) void bdep_kernel(const BState* __restrict__
 }
 
 // T = W with the flagged columns taken from the random block Z.
+template <class T>
 __global__ __launch_bounds__(kBlock) void breplace_kernel(const BTile* __restrict__ tiles,
                                                           const BState* __restrict__ st,
                                                           const int* __restrict__ depmask,
-                                                          const float* __restrict__ W,
+                                                          const T* __restrict__ W,
                                                           const float* __restrict__ Z,
-                                                          float* __restrict__ T) {
+                                                          T* __restrict__ out) {
   const BTile tl = tiles[blockIdx.x];
   if (!running(st[tl.sys])) return;
   const int c = threadIdx.x % P;
   const bool dep = (depmask[tl.sys] >> c) & 1;
   for (int r = tl.r0 + (int)threadIdx.x / P; r < tl.r0 + tl.nr; r += kBlock / P) {
     const size_t i = (size_t)r * P + c;
-    T[i] = dep ? Z[i] : W[i];
+    out[i] = dep ? T(Z[i]) : W[i];
   }
 }
 
-// Cholesky G = R^T R (R upper) and Rinv = R^{-1} (float32, matrix-core operand).
+// Cholesky G = R^T R (R upper) and Rinv = R^{-1} (inner precision, matrix-core operand).
 // When Rprev is given, Rout = R Rprev (the two Cholesky QR passes combined).
 // A pivot <= tau G_cc (or non-finite) is handled by `mode`:
 //   kCholStart: the start block failed (the system stops);
@@ -406,9 +490,10 @@ __global__ __launch_bounds__(kBlock) void breplace_kernel(const BTile* __restric
 //   kCholPass2: breakdown in the second pass; Rbrk receives Rprev.
 enum { kCholStart = 0, kCholPass1 = 1, kCholPass2 = 2 };
 
+template <class T>
 __global__ __launch_bounds__(kBlock) void bchol_kernel(BState* st, const double* __restrict__ Gd,
                                                        size_t gstride, const double* __restrict__ Rprev,
-                                                       double* __restrict__ Rout, float* __restrict__ Rinv_f,
+                                                       double* __restrict__ Rout, T* __restrict__ Rinv_f,
                                                        size_t rstride, double tau, int mode,
                                                        double* __restrict__ Rbrk) {
   const int s = blockIdx.x;
@@ -448,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void bchol_kernel(BState* st, const double*
     }
     __syncthreads();
   }
-  Rinv_f[(size_t)s * rstride + e] = float(sRi[e]);
+  Rinv_f[(size_t)s * rstride + e] = T(sRi[e]);
   if (Rout) {
     double v = sR[e];
     if (Rprev) {  // the two Cholesky QR passes combined: Rout = R Rprev
@@ -629,10 +714,11 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
 
 // Y = R^{-1} G over the K = 16 kblk leading rows (column-oriented
 // back-substitution), rounded into Yf[s][b][i * 16 + c] (row 16 b + i).
+template <class T>
 __global__ __launch_bounds__(kBlock) void bbacksolve_kernel(const BState* __restrict__ st,
                                                             const double* __restrict__ Hq,
                                                             size_t hstride, int ldh, double* Grhs,
-                                                            size_t gstride, float* Yf,
+                                                            size_t gstride, T* Yf,
                                                             size_t ystride) {
   const int s = blockIdx.x;
   const BState ss = st[s];
@@ -640,14 +726,14 @@ __global__ __launch_bounds__(kBlock) void bbacksolve_kernel(const BState* __rest
   const int K = 16 * ss.kblk;
   const double* H = Hq + (size_t)s * hstride;
   double* G = Grhs + (size_t)s * gstride;
-  float* Y = Yf + (size_t)s * ystride;
+  T* Y = Yf + (size_t)s * ystride;
   const int c = threadIdx.x % P;
   const int rg = threadIdx.x / P;
   for (int i = K - 1; i >= 0; --i) {
     if (threadIdx.x < P) {
       const double y = G[(size_t)i * P + c] / H[(size_t)i * ldh + i];
       G[(size_t)i * P + c] = y;
-      Y[(size_t)i * P + c] = float(y);
+      Y[(size_t)i * P + c] = T(y);
     }
     __syncthreads();
     const double y = G[(size_t)i * P + c];
@@ -723,7 +809,8 @@ struct BLayout {
   int ldh;
 };
 
-BLayout layout(const gmr_batch* b) {
+// Workspace layout; `elt` is the size of the inner precision (4 or 8 bytes).
+BLayout layout(const gmr_batch* b, size_t elt) {
   BLayout L;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = al(o + bytes); return at; };
@@ -744,23 +831,23 @@ BLayout layout(const gmr_batch* b) {
   L.gam = take(ns * P * 8);
   L.bnorm = take(ns * P * 8);
   L.dep = take(ns * 4);
-  L.V = take((size_t)(m + 1) * L.vstride * 4);
-  L.W = take(L.vstride * 4);
-  L.T = take(L.vstride * 4);
+  L.V = take((size_t)(m + 1) * L.vstride * elt);
+  L.W = take(L.vstride * elt);
+  L.T = take(L.vstride * elt);
   L.R64 = take(L.vstride * 8);
-  L.partial = take((size_t)b->max_tiles * L.pstride * 4);
+  L.partial = take((size_t)b->max_tiles * L.pstride * elt);
   L.rpart = take((size_t)b->max_tiles * P * 8);
   L.C1d = take(ns * L.cstride * 8);
   L.C2d = take(ns * L.cstride * 8);
   L.Cd = take(ns * L.cstride * 8);
-  L.Cf = take(ns * L.cstride * 4);
+  L.Cf = take(ns * L.cstride * elt);
   L.R1 = take(ns * PP * 8);
   L.Rn = take(ns * PP * 8);
   L.Hq = take(ns * L.hstride * 8);
   L.refl = take(ns * L.rfstride * 32 * 8);
   L.tau = take(ns * L.rfstride * 8);
   L.Grhs = take(ns * L.gstride * 8);
-  L.Yf = take(ns * L.ystride * 4);
+  L.Yf = take(ns * L.ystride * elt);
   L.end = o;
   return L;
 }
@@ -781,35 +868,54 @@ gmr_status launch_check(const char* what) {
 }
 
 // C[s][b] = V_b^T W for b < nblk, summed per system into Cd (and Cf).
-gmr_status dots(const BRun& R, const float* V, int nblk, const float* W, double* Cd, float* Cf) {
+// Float64 uses at most 8 blocks per group (its LDS partials are twice as big).
+template <class T>
+gmr_status dots(const BRun& R, const T* V, int nblk, const T* W, double* Cd, T* Cf) {
   const BTile* tl = R.at<BTile>(R.L.tiles);
   const BState* st = R.at<BState>(R.L.st);
-  float* part = R.at<float>(R.L.partial);
-  switch (R.b->gb) {
-    case 4: bdots_kernel<4><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
-    case 16: bdots_kernel<16><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
-    default: bdots_kernel<8><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
+  T* part = R.at<T>(R.L.partial);
+  const int gb = (sizeof(T) == 8 && R.b->gb > 8) ? 8 : R.b->gb;
+  switch (gb) {
+    case 4: bdots_kernel<T, 4><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
+    case 16: bdots_kernel<T, 16><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
+    default: bdots_kernel<T, 8><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
   }
   BT(launch_check("bdots_kernel"));
-  bfinish_c_kernel<<<dim3(R.b->nsys, nblk), kBlock, 0, R.s>>>(R.at<BSys>(R.L.sys), st, part, R.L.pstride, Cd, Cf,
-                                                                R.L.cstride);
+  bfinish_c_kernel<T><<<dim3(R.b->nsys, nblk), kBlock, 0, R.s>>>(R.at<BSys>(R.L.sys), st, part, R.L.pstride, Cd,
+                                                                   Cf, R.L.cstride);
   return launch_check("bfinish_c_kernel");
 }
 
-template <int MODE>
-gmr_status gemm(const BRun& R, const float* V, int nblk, const float* Cf, float* out, double* X64 = nullptr,
-                double tol = 0.0) {
-  bgemm_kernel<MODE><<<R.ntiles(), kBlock, (size_t)nblk * PP * sizeof(float), R.s>>>(R.at<BTile>(R.L.tiles), R.at<BState>(R.L.st), V, R.L.vstride,
-                                                     nblk, Cf, R.L.cstride, out, X64, R.at<double>(R.L.gam),
-                                                     R.at<double>(R.L.bnorm), tol);
+// Dynamic LDS of the block update: the nblk coefficient blocks (up to 130 KB
+// in float64 at the largest restart, within the 160 KB a workgroup may use).
+template <class T, int MODE>
+gmr_status gemm_launch(const BRun& R, const T* V, int nblk, const T* Cf, size_t cstride, T* out, double* X64,
+                       double tol) {
+  const size_t lds = (size_t)nblk * PP * sizeof(T);
+  if (lds > 64 * 1024) {
+    static bool raised = false;  // once per instantiation and process
+    if (!raised) {
+      BH(hipFuncSetAttribute(reinterpret_cast<const void*>(&bgemm_kernel<T, MODE>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxBlocks * PP * sizeof(T))));
+      raised = true;
+    }
+  }
+  bgemm_kernel<T, MODE><<<R.ntiles(), kBlock, lds, R.s>>>(R.at<BTile>(R.L.tiles), R.at<BState>(R.L.st), V,
+                                                          R.L.vstride, nblk, Cf, cstride, out, X64,
+                                                          R.at<double>(R.L.gam), R.at<double>(R.L.bnorm), tol);
   return launch_check("bgemm_kernel");
 }
 
+template <class T, int MODE>
+gmr_status gemm(const BRun& R, const T* V, int nblk, const T* Cf, T* out) {
+  return gemm_launch<T, MODE>(R, V, nblk, Cf, R.L.cstride, out, nullptr, 0.0);
+}
+
+template <class T>
 gmr_status chol(const BRun& R, const double* Gd, const double* Rprev, double* Rout, double tau, int mode) {
   const int ns = R.b->nsys;
-  bchol_kernel<<<ns, kBlock, 0, R.s>>>(R.at<BState>(R.L.st), Gd, R.L.cstride, Rprev, Rout,
-                                               R.at<float>(R.L.Cf), R.L.cstride, tau, mode,
-                                               R.at<double>(R.L.Rn));
+  bchol_kernel<T><<<ns, kBlock, 0, R.s>>>(R.at<BState>(R.L.st), Gd, R.L.cstride, Rprev, Rout, R.at<T>(R.L.Cf),
+                                          R.L.cstride, tau, mode, R.at<double>(R.L.Rn));
   return launch_check("bchol_kernel");
 }
 
@@ -817,17 +923,18 @@ gmr_status chol(const BRun& R, const double* Gd, const double* Rprev, double* Ro
 // orthonormal block is written to `dst`, and, for a block step, Rn = R2 R1.
 // A start block uses only a positivity threshold (its dependent columns were
 // replaced before); a block step breaks down below tau.
-gmr_status cholqr2(const BRun& R, float* T, float* dst, double tau, bool start) {
+template <class T>
+gmr_status cholqr2(const BRun& R, T* Tm, T* dst, double tau, bool start) {
   double* Cd = R.at<double>(R.L.Cd);
-  float* Cf = R.at<float>(R.L.Cf);
+  T* Cf = R.at<T>(R.L.Cf);
   const int m1 = start ? kCholStart : kCholPass1;
   const int m2 = start ? kCholStart : kCholPass2;
-  BT(dots(R, T, 1, T, Cd, nullptr));
-  BT(chol(R, Cd, nullptr, start ? nullptr : R.at<double>(R.L.R1), tau, m1));
-  BT(gemm<kSet>(R, T, 1, Cf, T));
-  BT(dots(R, T, 1, T, Cd, nullptr));
-  BT(chol(R, Cd, start ? nullptr : R.at<double>(R.L.R1), start ? nullptr : R.at<double>(R.L.Rn), tau, m2));
-  return gemm<kSet>(R, T, 1, Cf, dst);
+  BT(dots<T>(R, Tm, 1, Tm, Cd, nullptr));
+  BT(chol<T>(R, Cd, nullptr, start ? nullptr : R.at<double>(R.L.R1), tau, m1));
+  BT((gemm<T, kSet>(R, Tm, 1, Cf, Tm)));
+  BT(dots<T>(R, Tm, 1, Tm, Cd, nullptr));
+  BT(chol<T>(R, Cd, start ? nullptr : R.at<double>(R.L.R1), start ? nullptr : R.at<double>(R.L.Rn), tau, m2));
+  return gemm<T, kSet>(R, Tm, 1, Cf, dst);
 }
 
 gmr_status check_batch_csr(const gmr_csr* A, int dtype, int64_t rows) {
@@ -871,7 +978,10 @@ gmr_status batch_create(int32_t nsys, const int32_t* sys_rows, int32_t nrhs, int
 
 void batch_destroy(gmr_batch* b) { delete b; }
 
-size_t batch_workspace_bytes(const gmr_batch* b) { return b ? layout(b).end : 0; }
+size_t batch_workspace_bytes(const gmr_batch* b, int32_t inner_dtype) {
+  if (!b || (inner_dtype != GMR_F32 && inner_dtype != GMR_F64)) return 0;
+  return layout(b, inner_dtype == GMR_F64 ? 8 : 4).end;
+}
 
 gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_blocks) {
   if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: null batch");
@@ -891,7 +1001,11 @@ gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* gro
   return GMR_OK;
 }
 
-static gmr_status upload_tables(const BRun& R) {
+}  // extern "C"
+
+namespace {
+
+gmr_status upload_tables(const BRun& R) {
   BH(hipMemcpyAsync(R.at<BTile>(R.L.tiles), R.b->tiles.data(), R.b->tiles.size() * sizeof(BTile),
                     hipMemcpyHostToDevice, R.s));
   BH(hipMemcpyAsync(R.at<BSys>(R.L.sys), R.b->sys.data(), R.b->sys.size() * sizeof(BSys),
@@ -899,17 +1013,20 @@ static gmr_status upload_tables(const BRun& R) {
   return GMR_OK;
 }
 
-gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr* A32, const double* B,
-                                double* X, const float* Z, double tol, int32_t max_cycles, void* ws,
-                                size_t ws_bytes, gmr_batch_result* res, int32_t* sys_cycles,
-                                double* sys_rel_res, void* stream) {
+// The batched solve with inner precision T (float: GMRES-IR; double: plain
+// float64 block GMRES(m)).  Ain is A in precision T.
+template <class T>
+gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const gmr_csr* Ain, const double* B,
+                      double* X, const float* Z, double tol, int32_t max_cycles, void* ws, size_t ws_bytes,
+                      gmr_batch_result* res, int32_t* sys_cycles, double* sys_rel_res, void* stream) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (!b || !B || !X || !Z || !res) return gmr::fail(GMR_ERR_INVALID, "batch_gmres_ir_solve: null argument");
-  if (!(tol > 0.0) || max_cycles < 1) return gmr::fail(GMR_ERR_INVALID, "batch_gmres_ir_solve: bad tol or max_cycles");
+  const std::string nm(name);
+  if (!b || !B || !X || !Z || !res) return gmr::fail(GMR_ERR_INVALID, nm + ": null argument");
+  if (!(tol > 0.0) || max_cycles < 1) return gmr::fail(GMR_ERR_INVALID, nm + ": bad tol or max_cycles");
   BT(check_batch_csr(A64, GMR_F64, b->rows));
-  BT(check_batch_csr(A32, GMR_F32, b->rows));
-  BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
-  if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_gmres_ir_solve: workspace too small");
+  BT(check_batch_csr(Ain, sizeof(T) == 8 ? GMR_F64 : GMR_F32, b->rows));
+  BRun R{b, layout(b, sizeof(T)), (char*)ws, (hipStream_t)stream};
+  if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, nm + ": workspace too small");
   const int ns = b->nsys;
   const int m = b->m;
   const int nt = R.ntiles();
@@ -919,15 +1036,15 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
   BState* st = R.at<BState>(R.L.st);
   double* gam = R.at<double>(R.L.gam);
   double* bnorm = R.at<double>(R.L.bnorm);
-  float* V = R.at<float>(R.L.V);
-  float* W = R.at<float>(R.L.W);
-  float* T = R.at<float>(R.L.T);
+  T* V = R.at<T>(R.L.V);
+  T* W = R.at<T>(R.L.W);
+  T* Tm = R.at<T>(R.L.T);
   double* R64 = R.at<double>(R.L.R64);
   double* rpart = R.at<double>(R.L.rpart);
   double* Cd = R.at<double>(R.L.Cd);
   double* C1d = R.at<double>(R.L.C1d);
   double* C2d = R.at<double>(R.L.C2d);
-  float* Cf = R.at<float>(R.L.Cf);
+  T* Cf = R.at<T>(R.L.Cf);
   std::vector<BState> hst(ns);
   for (auto& h : hst) h = BState{1, 0, 0, 0, 0, 0};
   BH(hipMemcpyAsync(st, hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
@@ -962,7 +1079,7 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
         if (hst[s].kblk > 0) block_iters += hst[s].kblk;
     if (failed) {
       status = GMR_ERR_NONFINITE;
-      gmr::fail(GMR_ERR_NONFINITE, "batch_gmres_ir_solve: a start block could not be orthonormalised");
+      gmr::fail(GMR_ERR_NONFINITE, nm + ": a start block could not be orthonormalised");
       break;
     }
     if (active == 0) {
@@ -975,43 +1092,40 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
     ++total_cycles;
     // --- start block: W = R/gamma, dependent columns from Z, Cholesky QR twice
     bcycle_reset_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, st);
-    bstart_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, R64, gam, W);
+    bstart_kernel<T><<<nt, kBlock, 0, R.s>>>(tl, st, R64, gam, W);
     BT(launch_check("bstart_kernel"));
-    BT(dots(R, W, 1, W, Cd, nullptr));
+    BT(dots<T>(R, W, 1, W, Cd, nullptr));
     bdep_kernel<<<ns, kBlock, 0, R.s>>>(st, Cd, R.L.cstride, R.at<int>(R.L.dep), 1e-5);
     BT(launch_check("bdep_kernel"));
-    breplace_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, R.at<int>(R.L.dep), W, Z, T);
+    breplace_kernel<T><<<nt, kBlock, 0, R.s>>>(tl, st, R.at<int>(R.L.dep), W, Z, Tm);
     BT(launch_check("breplace_kernel"));
-    BT(cholqr2(R, T, V, 1e-12, true));
-    BT(dots(R, V, 1, W, Cd, nullptr));  // R0 = V0^T W
+    BT(cholqr2<T>(R, Tm, V, 1e-12, true));
+    BT(dots<T>(R, V, 1, W, Cd, nullptr));  // R0 = V0^T W
     binit_rhs_kernel<<<ns, kBlock, 0, R.s>>>(st, Cd, R.L.cstride, R.at<double>(R.L.Grhs), R.L.gstride);
     BT(launch_check("binit_rhs_kernel"));
     // --- m block steps
     for (int j = 0; j < m; ++j) {
       const int nb = j + 1;
-      bspmm_kernel<<<nt, kBlock, 0, R.s>>>(tl, st, A32->row_ptr, A32->col_idx, (const float*)A32->val,
-                                           V + (size_t)j * R.L.vstride, W);
+      bspmm_kernel<T><<<nt, kBlock, 0, R.s>>>(tl, st, Ain->row_ptr, Ain->col_idx, (const T*)Ain->val,
+                                              V + (size_t)j * R.L.vstride, W);
       BT(launch_check("bspmm_kernel"));
-      BT(dots(R, V, nb, W, C1d, Cf));
-      BT(gemm<kSub>(R, V, nb, Cf, W));
-      BT(dots(R, V, nb, W, C2d, Cf));
-      BT(gemm<kSub>(R, V, nb, Cf, W));
-      BT(cholqr2(R, W, V + (size_t)(j + 1) * R.L.vstride, 1e-5, false));
+      BT(dots<T>(R, V, nb, W, C1d, Cf));
+      BT((gemm<T, kSub>(R, V, nb, Cf, W)));
+      BT(dots<T>(R, V, nb, W, C2d, Cf));
+      BT((gemm<T, kSub>(R, V, nb, Cf, W)));
+      BT(cholqr2<T>(R, W, V + (size_t)(j + 1) * R.L.vstride, 1e-5, false));
       bls_kernel<<<ns, kWave, 0, R.s>>>(j, st, C1d, C2d, R.L.cstride, R.at<double>(R.L.Rn),
                                         R.at<double>(R.L.Hq), R.L.hstride, R.L.ldh, R.at<double>(R.L.refl),
                                         R.at<double>(R.L.tau), R.L.rfstride, R.at<double>(R.L.Grhs), R.L.gstride);
       BT(launch_check("bls_kernel"));
     }
     // --- solution update and the next residual
-    float* Yf = R.at<float>(R.L.Yf);
-    bbacksolve_kernel<<<ns, kBlock, 0, R.s>>>(st, R.at<double>(R.L.Hq), R.L.hstride, R.L.ldh,
-                                              R.at<double>(R.L.Grhs), R.L.gstride, Yf, R.L.ystride);
+    T* Yf = R.at<T>(R.L.Yf);
+    bbacksolve_kernel<T><<<ns, kBlock, 0, R.s>>>(st, R.at<double>(R.L.Hq), R.L.hstride, R.L.ldh,
+                                                 R.at<double>(R.L.Grhs), R.L.gstride, Yf, R.L.ystride);
     BT(launch_check("bbacksolve_kernel"));
     // the update reads C from Yf, laid out like the Gram-Schmidt coefficients
-    bgemm_kernel<kXupd><<<nt, kBlock, (size_t)m * PP * sizeof(float), R.s>>>(tl, st, V, R.L.vstride, 0, Yf,
-                                                                              R.L.ystride, nullptr, X, gam,
-                                                                              bnorm, tol);
-    BT(launch_check("bgemm_kernel<xupd>"));
+    BT((gemm_launch<T, kXupd>(R, V, m, Yf, R.L.ystride, nullptr, X, tol)));
     BT(residual());
   }
   BH(hipStreamSynchronize(R.s));
@@ -1035,13 +1149,32 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
   return status;
 }
 
+}  // namespace
+
+extern "C" {
+
+gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr* A32, const double* B,
+                                double* X, const float* Z, double tol, int32_t max_cycles, void* ws,
+                                size_t ws_bytes, gmr_batch_result* res, int32_t* sys_cycles,
+                                double* sys_rel_res, void* stream) {
+  return solve_impl<float>("batch_gmres_ir_solve", b, A64, A32, B, X, Z, tol, max_cycles, ws, ws_bytes, res,
+                           sys_cycles, sys_rel_res, stream);
+}
+
+gmr_status batch_gmres_solve(gmr_batch* b, const gmr_csr* A64, const double* B, double* X, const float* Z,
+                             double tol, int32_t max_cycles, void* ws, size_t ws_bytes, gmr_batch_result* res,
+                             int32_t* sys_cycles, double* sys_rel_res, void* stream) {
+  return solve_impl<double>("batch_gmres_solve", b, A64, A64, B, X, Z, tol, max_cycles, ws, ws_bytes, res,
+                            sys_cycles, sys_rel_res, stream);
+}
+
 // Times the block Gram-Schmidt contraction pair (dots + update over nblk = m/2
 // blocks) for every candidate tiling on the batch's own buffers and keeps the
 // fastest.  The workspace is the solve's; its contents are overwritten.
 gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,
                           int32_t* best_group_blocks, double* best_ms, void* stream) {
   if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_autotune: null batch");
-  BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
+  BRun R{b, layout(b, 4), (char*)ws, (hipStream_t)stream};
   if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_autotune: workspace too small");
   const int ns = b->nsys;
   std::vector<BState> hst(ns, BState{1, 0, 0, 0, 0, 0});
@@ -1066,9 +1199,12 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
       float ms = 0.f;
       for (int rep = 0; rep < 3; ++rep) {  // first repetition warms up
         if (hipEventRecord(e0, R.s) != hipSuccess) { status = GMR_ERR_HIP; break; }
-        if ((status = dots(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd),
-                           R.at<float>(R.L.Cf))) != GMR_OK) break;
-        if ((status = gemm<kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))) != GMR_OK) break;
+        if ((status = dots<float>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd),
+                                  R.at<float>(R.L.Cf))) != GMR_OK)
+          break;
+        if ((status = gemm<float, kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))) !=
+            GMR_OK)
+          break;
         if (hipEventRecord(e1, R.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { status = GMR_ERR_HIP; break; }
         float t = 0.f;
         (void)hipEventElapsedTime(&t, e0, e1);
@@ -1100,18 +1236,18 @@ gmr_status batch_bcgs_step(gmr_batch* b, const float* Vin, int32_t nblk, float* 
                            size_t ws_bytes, void* stream) {
   if (!b || !Vin || !W || !C || nblk < 1 || nblk > b->m + 1)
     return gmr::fail(GMR_ERR_INVALID, "batch_bcgs_step: bad arguments");
-  BRun R{b, layout(b), (char*)ws, (hipStream_t)stream};
+  BRun R{b, layout(b, 4), (char*)ws, (hipStream_t)stream};
   if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, "batch_bcgs_step: workspace too small");
   const int ns = b->nsys;
   std::vector<BState> hst(ns, BState{1, 0, 0, 0, 0, 0});
   BH(hipMemcpyAsync(R.at<BState>(R.L.st), hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
   BT(upload_tables(R));
   BH(hipMemcpyAsync(R.at<float>(R.L.V), Vin, (size_t)nblk * R.L.vstride * 4, hipMemcpyDeviceToDevice, R.s));
-  BT(dots(R, R.at<float>(R.L.V), nblk, W, R.at<double>(R.L.Cd), R.at<float>(R.L.Cf)));
+  BT(dots<float>(R, R.at<float>(R.L.V), nblk, W, R.at<double>(R.L.Cd), R.at<float>(R.L.Cf)));
   for (int s = 0; s < ns; ++s)
     BH(hipMemcpyAsync(C + (size_t)s * nblk * PP, R.at<double>(R.L.Cd) + (size_t)s * R.L.cstride,
                       (size_t)nblk * PP * 8, hipMemcpyDeviceToDevice, R.s));
-  return gemm<kSub>(R, R.at<float>(R.L.V), nblk, R.at<float>(R.L.Cf), W);
+  return gemm<float, kSub>(R, R.at<float>(R.L.V), nblk, R.at<float>(R.L.Cf), W);
 }
 
 }  // extern "C"

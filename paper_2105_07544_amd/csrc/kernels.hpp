@@ -94,9 +94,10 @@ __device__ __forceinline__ void load_quad(const int* __restrict__ ci, const T* _
 // Computes, for thread t of the block, the dot product of row (r0 + t) with x
 // (x scaled by `s` when SCALED).  Returns 0 for threads past the last row.
 // The block's nonzeros are processed in passes of kSpmvChunk entries that
-// start on a multiple of 4: each thread loads two quads of (col, val) with
-// vector loads, gathers x for the entries that belong to the block, stores the
-// rounded products in LDS, and then adds up its own row in ascending k.
+// start on a multiple of 4: each thread loads up to two quads of (col, val)
+// with vector loads (none past the block's last nonzero), gathers x for the
+// entries that belong to the block, stores the rounded products in LDS, and
+// then adds up its own row in ascending k.
 template <class T, bool SCALED>
 __device__ __forceinline__ T spmv_row(int n, int r0, const int* __restrict__ rp,
                                       const int* __restrict__ ci, const T* __restrict__ val,
@@ -118,7 +119,18 @@ __device__ __forceinline__ T spmv_row(int n, int r0, const int* __restrict__ rp,
     int col[Q][4];
     T a[Q][4];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) load_quad<T>(ci, val, base + 4 * (t + q * kBlock), nnz, col[q], a[q]);
+    for (int q = 0; q < Q; ++q) {
+      const int kk = base + 4 * (t + q * kBlock);
+      if (kk < k1) {
+        load_quad<T>(ci, val, kk, nnz, col[q], a[q]);
+      } else {  // the quad lies past the block's last row: nothing to load
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          col[q][i] = 0;
+          a[q][i] = T(0);
+        }
+      }
+    }
     T xv[Q][4];
 #pragma unroll
     for (int q = 0; q < Q; ++q)

@@ -88,6 +88,44 @@ def test_small_batch_matches_oracle():
         off += ns
 
 
+def test_float64_batched_solve_matches_oracle():
+    systems = W.config4_batch(count=4, nrhs=16, side_lo=12, side_hi=28, seed=16)
+    A, B, Z, A64, A32 = batch_inputs(systems)
+    m = 8
+    b = G.Batch([s["A"].n for s in systems], restart=m)
+    assert b.workspace_bytes(G.GMR_F64) > b.workspace_bytes(G.GMR_F32) > 0
+    ws = G.alloc_workspace(b.workspace_bytes(G.GMR_F64), DEV)
+    Bd = torch.from_numpy(B).to(DEV)
+    X = torch.zeros_like(Bd)
+    Zd = torch.from_numpy(Z.astype(np.float32)).to(DEV)
+    out = b.solve(A64, None, Bd, X, Zd, ws, tol=1e-12, max_cycles=200)
+    say(out["status_name"], out["cycles"], out["max_rel_res"], list(out["sys_cycles"]))
+    assert out["status"] == 0 and out["max_rel_res"] <= 1e-12
+    Xh = host(X)
+    off = 0
+    for s, sy in enumerate(systems):
+        ns = sy["A"].n
+        res = np.linalg.norm(sy["B"] - O.spmm(sy["A"], Xh[off:off + ns], np.float64), axis=0) / \
+            np.linalg.norm(sy["B"], axis=0)
+        assert np.all(res <= 1e-12), (s, res.max())
+        ref = O.block_gmres_ir(sy["A"], sy["B"], m, 1e-12, 200, Z=Z[off:off + ns].astype(np.float32),
+                               inner=np.float64)
+        say("system", s, "cycles gpu", out["sys_cycles"][s], "oracle", ref.cycles)
+        assert ref.converged
+        assert abs(int(out["sys_cycles"][s]) - ref.cycles) <= max(1, 0.1 * ref.cycles)
+        off += ns
+
+
+def test_float64_workspace_too_small_is_an_error():
+    systems = W.config4_batch(count=2, nrhs=16, side_lo=12, side_hi=16, seed=17)
+    A, B, Z, A64, A32 = batch_inputs(systems)
+    b = G.Batch([s["A"].n for s in systems], restart=4)
+    ws = G.alloc_workspace(b.workspace_bytes(G.GMR_F32), DEV)  # the float32 size
+    Bd = torch.from_numpy(B).to(DEV)
+    with pytest.raises(G.GmresError):
+        b.solve(A64, None, Bd, torch.zeros_like(Bd), torch.from_numpy(Z.astype(np.float32)).to(DEV), ws)
+
+
 def test_autotune_picks_a_candidate_and_solves():
     systems = W.config4_batch(count=6, nrhs=16, side_lo=20, side_hi=60, seed=15)
     A, B, Z, A64, A32 = batch_inputs(systems)

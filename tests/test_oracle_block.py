@@ -55,6 +55,24 @@ def test_block_gmres_ir_reaches_tolerance_on_small_batch_system():
         assert np.allclose(out.X, Xs, rtol=0, atol=1e-6 * np.abs(Xs).max())
 
 
+def test_float64_block_gmres_reaches_dense_solution():
+    sys = W.config4_batch(count=2, nrhs=4, side_lo=12, side_hi=20, seed=11)
+    for s in sys:
+        out = O.block_gmres_ir(s["A"], s["B"], 10, 1e-12, 60, inner=np.float64)
+        assert out.converged and np.all(out.rel_res <= 1e-12)
+        Xs = np.linalg.solve(s["A"].to_dense(), s["B"])
+        assert np.allclose(out.X, Xs, rtol=0, atol=1e-8 * np.abs(Xs).max())
+        # one float64 cycle from X = 0 reaches the block-Krylov minimum of its
+        # restart length (the property pinned on block_arnoldi above)
+        one = O.block_gmres_ir(s["A"], s["B"], 3, 1e-30, 1, inner=np.float64)
+        D = s["A"].to_dense()
+        K = np.concatenate([np.linalg.matrix_power(D, i) @ s["B"] for i in range(3)], axis=1)
+        for c in range(4):
+            z, *_ = np.linalg.lstsq(D @ K, s["B"][:, c], rcond=None)
+            best = np.linalg.norm(s["B"][:, c] - D @ K @ z) / np.linalg.norm(s["B"][:, c])
+            assert np.isclose(one.rel_res[c], best, rtol=1e-6), (c, one.rel_res[c], best)
+
+
 def test_cholqr2_detects_rank_deficiency():
     W_ = np.ones((10, 3))
     _, _, ok = O.cholqr2(W_)
