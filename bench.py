@@ -47,6 +47,85 @@ def host_csr(A):
     return sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.n, A.n))
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2105_07544_amd", "csrc", f) for f in ("kernels.hpp", "device_common.hpp")]
+
+
+def kernel_source_hash() -> str:
+    """sha256 of the single-system kernel sources: a stored counter figure is
+    used only while these are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the hardware-counter
+    summary, or None when there is none or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            entry = json.load(fh)[workload][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    if entry.get("source_sha256") != kernel_source_hash():
+        return None
+    return entry["bytes_per_launch"]
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, kernel: str, patterns, calib_mib: int):
+    """Turns two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) into bytes per launch of the kernel family: each counter is scaled
+    by what it reads for the element-wise negation of calib_mib MiB (which
+    reads and writes exactly that much).  Writes the entry to the traffic file
+    and prints a markdown table."""
+    import csv
+    from collections import defaultdict
+
+    def load(path):
+        d = defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                d[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return d
+    f, w = load(fetch_csv), load(write_csv)
+    calib = [n for n in f if "neg_kernel" in n]
+    if not calib:
+        raise SystemExit("no calibration kernel in the counter runs (run bench.py with --copy-calibration)")
+    known_kib = calib_mib * 1024.0
+    ff = known_kib / (sum(f[calib[0]]) / len(f[calib[0]]))
+    fw = known_kib / (sum(w[calib[0]]) / len(w[calib[0]]))
+    rows, tot, cnt = [], 0.0, 0
+    for name in sorted(n for n in f if any(p in n for p in patterns)):
+        vf, vw = f[name], w.get(name, [])
+        if len(vf) != len(vw):
+            raise SystemExit(f"dispatch counts differ between the two runs for {name}")
+        b = [1024.0 * (a * ff + c * fw) for a, c in zip(vf, vw)]
+        tot += sum(b)
+        cnt += len(b)
+        rows.append((name.split("(")[0].replace("void ", ""), len(b), sum(vf) / len(vf), sum(vw) / len(vw),
+                     sum(b) / len(b)))
+    per_launch = tot / cnt
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        data = {}
+    data.setdefault(workload, {})[kernel] = {
+        "bytes_per_launch": per_launch, "launches": cnt, "fetch_scale": ff, "write_scale": fw,
+        "source_sha256": kernel_source_hash()}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    print(f"scale factors (negation of {calib_mib} MiB): FETCH_SIZE x {ff:.4f}, WRITE_SIZE x {fw:.4f}\n")
+    print("| kernel | launches | FETCH_SIZE KiB/launch | WRITE_SIZE KiB/launch | HBM bytes/launch (scaled) |")
+    print("|---|---|---|---|---|")
+    for r in rows:
+        print(f"| `{r[0]}` | {r[1]} | {r[2]:.1f} | {r[3]:.1f} | {r[4]:.4g} |")
+    print(f"\nall {kernel} launches ({', '.join(patterns)}): {cnt}, mean HBM bytes per launch {per_launch:.6g}")
+
+
 def cpu_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -196,7 +275,7 @@ def single_system(args, kind):
         "graph": graph,
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "launches": prof_launches,
+                     "traffic": stored_traffic(dominant, kind), "launches": prof_launches,
                      "avg_launch_us": round(1e3 * prof_ms / max(1, prof_launches), 2),
                      "bytes_per_launch": round(prof_bytes / max(1, prof_launches))},
         "kernel_breakdown": breakdown,
@@ -347,7 +426,15 @@ def main():
                     help="run three plain copies of MIB MiB first (counter scale factor)")
     ap.add_argument("--graph", type=int, default=0,
                     help="replay each restart cycle as a hipGraph (no per-kernel events then)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no run: turn two counter runs of this script into the stored traffic figure")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        dom = "poly_step" if args.workload == "convdiff" else "cgs_update_dots"
+        pats = {"poly_step": ["poly_real_kernel<float", "poly_pair1_kernel<float", "poly_pair2_kernel<float"],
+                "cgs_update_dots": ["cgs_update_dots_kernel<float"]}[dom]
+        summarize_pmc(*args.summarize_pmc, args.workload, dom, pats, args.copy_calibration or 1024)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
               "multi-GPU path; the sharded design is described in DESIGN.md", file=sys.stderr)

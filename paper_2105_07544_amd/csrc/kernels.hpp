@@ -67,18 +67,24 @@ struct CycleState {
 // Loads the 4 consecutive CSR entries starting at kk (a multiple of 4) with
 // 16-byte vector loads when they lie inside the arrays (col_idx and val are
 // 16-byte aligned, which the host checks), element by element at the end.
+// The matrix is streamed once per product, so the vector loads are marked
+// non-temporal: they do not displace the gathered x from the caches.
+typedef int ivec4_t __attribute__((ext_vector_type(4)));
+typedef float fvec4_t __attribute__((ext_vector_type(4)));
+typedef double dvec2_t __attribute__((ext_vector_type(2)));
+
 template <class T>
 __device__ __forceinline__ void load_quad(const int* __restrict__ ci, const T* __restrict__ val,
                                           int kk, int nnz, int (&c)[4], T (&a)[4]) {
   if (kk + 4 <= nnz) {
-    const int4 c4 = *reinterpret_cast<const int4*>(ci + kk);
+    const ivec4_t c4 = __builtin_nontemporal_load(reinterpret_cast<const ivec4_t*>(ci + kk));
     c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
     if constexpr (sizeof(T) == 4) {
-      const float4 a4 = *reinterpret_cast<const float4*>(val + kk);
+      const fvec4_t a4 = __builtin_nontemporal_load(reinterpret_cast<const fvec4_t*>(val + kk));
       a[0] = a4.x; a[1] = a4.y; a[2] = a4.z; a[3] = a4.w;
     } else {
-      const double2 a0 = *reinterpret_cast<const double2*>(val + kk);
-      const double2 a1 = *reinterpret_cast<const double2*>(val + kk + 2);
+      const dvec2_t a0 = __builtin_nontemporal_load(reinterpret_cast<const dvec2_t*>(val + kk));
+      const dvec2_t a1 = __builtin_nontemporal_load(reinterpret_cast<const dvec2_t*>(val + kk + 2));
       a[0] = a0.x; a[1] = a0.y; a[2] = a1.x; a[3] = a1.y;
     }
   } else {
