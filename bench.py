@@ -208,28 +208,33 @@ def single_system(args, kind):
     torch.cuda.synchronize()
     graph = bool(args.graph)
 
+    # small systems run each restart cycle as one single-block kernel
+    pers = (args.persistent == 1) or (args.persistent < 0 and kind == "laplace2d")
+
     def ir(prof="none", g=None):
         x.zero_()
         return G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir,
-                                P=P32, prof=prof, graph=graph if g is None else g)[1]
+                                P=P32, prof=prof, graph=graph if g is None else g, persistent=pers)[1]
 
     def f64(prof="none", g=None):
         x.zero_()
         return G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_64, P=P64,
-                             prof=prof, graph=graph if g is None else g)[1]
+                             prof=prof, graph=graph if g is None else g, persistent=pers)[1]
 
     log("bench: warmup")
     unprof = [ir().seconds for _ in range(args.warmup)]
     # timed region: K complete GMRES-IR solves; every launch of the dominant
-    # kernel is bracketed by HIP events on the solver's stream (graph replay
-    # has no per-kernel events, so with --graph 1 K more eager solves give them)
+    # kernel is bracketed by HIP events on the solver's stream (graph replay and
+    # the single-block cycle have no per-kernel events: then K more multi-kernel
+    # solves give them)
     log(f"bench: timing {args.steps} GMRES-IR solves")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [ir(prof="none" if graph else dominant) for _ in range(args.steps)]
+    eager_events = not (graph or pers)  # graph replay and the single-block cycle have no per-kernel events
+    res = [ir(prof=dominant if eager_events else "none") for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_ir = (time.perf_counter() - t0) / args.steps
-    pres = [ir(prof=dominant, g=False) for _ in range(args.steps)] if graph else res
+    pres = res if eager_events else [ir(prof=dominant, g=False) for _ in range(args.steps)]
     last = res[-1]
     assert all(r.converged for r in res), [r.status_name for r in res]
     xh = x.cpu().numpy()
@@ -272,7 +277,7 @@ def single_system(args, kind):
         "fp64_iters": r64[-1].iters, "fp64_cycles": r64[-1].cycles,
         "rel_res": rel, "forward_error": fwd,
         "ms_per_step_unprofiled": round(1e3 * float(np.median(unprof)), 3) if unprof else None,
-        "graph": graph,
+        "graph": graph, "persistent_cycle": pers,
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": stored_traffic(dominant, kind), "launches": prof_launches,
@@ -424,6 +429,8 @@ def main():
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run three plain copies of MIB MiB first (counter scale factor)")
+    ap.add_argument("--persistent", type=int, default=-1,
+                    help="one single-block kernel per restart cycle (1), off (0), or -1: on for laplace2d")
     ap.add_argument("--graph", type=int, default=0,
                     help="replay each restart cycle as a hipGraph (no per-kernel events then)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

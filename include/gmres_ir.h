@@ -82,6 +82,13 @@ typedef struct {
  * restart (ignored while profiling).  The solve then runs on a library-owned
  * non-blocking stream after `stream` has drained; results are the same bits. */
 #define GMR_FLAG_GRAPH 1
+/* gmr_params.flags: for a small system (n <= 32768) without a polynomial,
+ * run each whole restart cycle (cast, inner iterations, update, residual) as
+ * one kernel of one block, with block barriers instead of kernel boundaries:
+ * one launch per cycle instead of about eight per iteration.  Ignored when it
+ * does not apply (larger n, polynomial, profiling, GMR_FLAG_GRAPH); the
+ * arithmetic is the same, summed in a different grouping. */
+#define GMR_FLAG_PERSISTENT 2
 
 typedef struct {
   int32_t status;            /* gmr_status                                                 */
@@ -227,6 +234,13 @@ size_t batch_workspace_bytes(const gmr_batch* b, int32_t inner_dtype);
  * basis blocks accumulated per pass (4, 8 or 16). */
 gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_blocks);
 gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* group_blocks);
+
+/* With on != 0, the solves of this batch capture one restart cycle (start
+ * block, m block steps, update and residual: the same launches with the same
+ * arguments every cycle) as a hipGraph and replay it once per cycle.  They
+ * then run on a library-owned stream after draining the caller's stream.
+ * Results are identical to the eager launches. */
+gmr_status batch_set_graph(gmr_batch* b, int32_t on);
 
 /* Times the block Gram-Schmidt contraction pair for every candidate tiling on
  * the batch's own workspace (its contents are overwritten), keeps the fastest

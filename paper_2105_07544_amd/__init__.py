@@ -200,10 +200,10 @@ class SolveResult:
         return self.status == 0
 
 
-def _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph=False):
+def _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph=False, persistent=False):
+    flags = (_capi.GMR_FLAG_GRAPH if graph else 0) | (_capi.GMR_FLAG_PERSISTENT if persistent else 0)
     return _capi.gmr_params(int(restart), float(tol), int(max_iters), int(max_cycles),
-                            int(stagnation_cycles), PROF[prof] if isinstance(prof, str) else int(prof),
-                            _capi.GMR_FLAG_GRAPH if graph else 0)
+                            int(stagnation_cycles), PROF[prof] if isinstance(prof, str) else int(prof), flags)
 
 
 def _result(res: _capi.gmr_result, hist: np.ndarray) -> SolveResult:
@@ -216,11 +216,12 @@ def _result(res: _capi.gmr_result, hist: np.ndarray) -> SolveResult:
 def gmres_solve(A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None, *, restart: int = 50,
                 tol: float = 1e-10, max_iters: int = 100000, max_cycles: int = 0,
                 P: Optional[Poly] = None, ws: Optional[torch.Tensor] = None, prof="none",
-                graph: bool = False):
-    """Restarted GMRES(m) in A's precision.  x (x0, updated in place) defaults to 0."""
+                graph: bool = False, persistent: bool = False):
+    """Restarted GMRES(m) in A's precision.  x (x0, updated in place) defaults to 0.
+    persistent: one single-block kernel per restart cycle for small systems."""
     if x is None:
         x = torch.zeros_like(b)
-    prm = _params(restart, tol, max_iters, max_cycles, 0, prof, graph)
+    prm = _params(restart, tol, max_iters, max_cycles, 0, prof, graph, persistent)
     if ws is None:
         ws = alloc_workspace(workspace_bytes(A.n, restart, A.dtype, P is not None), A.device)
     cap = max_cycles + 1 if max_cycles > 0 else 4096
@@ -237,11 +238,13 @@ def gmres_solve(A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None,
 def gmres_ir_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None, *,
                    restart: int = 50, tol: float = 1e-10, max_iters: int = 100000, max_cycles: int = 0,
                    stagnation_cycles: int = 0, P: Optional[Poly] = None,
-                   ws: Optional[torch.Tensor] = None, prof="none", graph: bool = False):
-    """GMRES-IR: float32 inner GMRES(m) on A32, float64 residual and update on A64."""
+                   ws: Optional[torch.Tensor] = None, prof="none", graph: bool = False,
+                   persistent: bool = False):
+    """GMRES-IR: float32 inner GMRES(m) on A32, float64 residual and update on A64.
+    persistent: one single-block kernel per restart cycle for small systems."""
     if x is None:
         x = torch.zeros_like(b)
-    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph)
+    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph, persistent)
     if ws is None:
         ws = alloc_workspace(workspace_bytes(A64.n, restart, GMR_F32, P is not None), A64.device)
     cap = max_cycles + 1 if max_cycles > 0 else 4096
@@ -311,6 +314,10 @@ class Batch:
 
     def set_tiling(self, tile_rows: int, group_blocks: int):
         check(lib().batch_set_tiling(self._h, tile_rows, group_blocks))
+
+    def set_graph(self, on: bool):
+        """Replay each restart cycle as a captured hipGraph (same results)."""
+        check(lib().batch_set_graph(self._h, 1 if on else 0))
 
     def tiling(self):
         t, g = C.c_int32(), C.c_int32()

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libgmresir.so")
 
 GMR_F32, GMR_F64 = 0, 1
 GMR_FLAG_GRAPH = 1
+GMR_FLAG_PERSISTENT = 2
 STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", -1: "GMR_ERR_INVALID",
           -2: "GMR_ERR_HIP", -3: "GMR_ERR_WORKSPACE", -4: "GMR_ERR_NONFINITE",
           -5: "GMR_ERR_UNSUPPORTED"}
@@ -23,7 +24,7 @@ EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "po
             "poly_prec_destroy", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
             "gmres_ir_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
-            "batch_set_tiling", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve", "batch_gmres_solve",
+            "batch_set_tiling", "batch_set_graph", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve", "batch_gmres_solve",
             "batch_bcgs_step", "mlp_param_count", "mlp_workspace_bytes", "mlp_forward",
             "mlp_loss_grad", "mlp_adam_step", "matrix_stats"]
 
@@ -105,6 +106,8 @@ def load() -> C.CDLL:
     lib.batch_workspace_bytes.restype = C.c_size_t
     lib.batch_set_tiling.argtypes = [P, C.c_int32, C.c_int32]
     lib.batch_set_tiling.restype = st
+    lib.batch_set_graph.argtypes = [P, C.c_int32]
+    lib.batch_set_graph.restype = st
     lib.batch_get_tiling.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.batch_get_tiling.restype = st
     lib.batch_autotune.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_int32), C.POINTER(C.c_int32),

@@ -567,13 +567,21 @@ __global__ __launch_bounds__(kBlock) void binit_rhs_kernel(const BState* __restr
 
 // One block column of the block Hessenberg matrix, [C1 + C2; R], reduced by the
 // earlier block Householder reflectors, then a new set of 16 reflectors on its
-// 32 x 16 panel; the same reflectors are applied to Grhs.  Lane c < 16 of the
-// single wave owns column c and keeps a 32-row window of it in registers: the
-// reflectors of block column bi act on rows 16 bi .. 16 bi + 31 only, so after
-// block column bi the top 16 rows of the window are final and the window
-// slides down by 16 rows.  After the last earlier block column the window is
-// the new panel.  Reflector t of block column i acts on rows 16 i + t ..
-// 16 i + 31 and is stored as v (v_t = 1) with its tau.
+// 32 x 16 panel; the same reflectors are applied to Grhs.  The wave's 64 lanes
+// form 16 quads, quad c owning column c: lane q of the quad keeps rows
+// 8q .. 8q+7 of a 32-row window of the column in registers, and a reflector's
+// dot product is the quad's sum of four 8-row partial sums.  The reflectors of
+// block column bi act on rows 16 bi .. 16 bi + 31 only, so after block column
+// bi the top 16 rows of the window are final and the window slides down by 16
+// rows; after the last earlier block column it is the new panel.  Reflector t
+// of block column i acts on rows 16 i + t .. 16 i + 31 and is stored as v
+// (v_t = 1, entries above t unused) with its tau.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += xor_lane<1>(v);
+  v += xor_lane<2>(v);
+  return v;
+}
+
 __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const double* __restrict__ C1d,
                                                     const double* __restrict__ C2d, size_t cstride,
                                                     const double* __restrict__ Rn, double* Hq,
@@ -586,124 +594,130 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
   __shared__ double s_tau[P];
   __shared__ double s_v[32];
   __shared__ double s_t;
-  const int c = threadIdx.x;
-  const bool own = c < P;
-  const int cc = own ? c : 0;  // the other lanes shadow column 0 and write nothing
+  const int lane = threadIdx.x;
+  const int col = lane / 4;
+  const int q = lane % 4;
   double* H = Hq + (size_t)s * hstride;
   double* RF = refl + (size_t)s * rfstride * 32;   // [blockcol][32 rows][16 refl]
   double* TU = tauv + (size_t)s * rfstride;       // [blockcol][16]
   double* G = Grhs + (size_t)s * gstride;          // [row][16]
-  double* hcol = H + (size_t)(16 * j + cc) * ldh;
+  double* hcol = H + (size_t)(16 * j + col) * ldh;
   const double* C1 = C1d + (size_t)s * cstride;
   const double* C2 = C2d + (size_t)s * cstride;
   const double* Rs = Rn + (size_t)s * PP;
   // entry of the new column in row 16 b + i
   auto entry = [&](int b, int i) -> double {
-    if (b <= j) return C1[b * PP + i * P + cc] + C2[b * PP + i * P + cc];
-    if (b == j + 1) return Rs[i * P + cc];
+    if (b <= j) return C1[b * PP + i * P + col] + C2[b * PP + i * P + col];
+    if (b == j + 1) return Rs[i * P + col];
     return 0.0;
   };
-  double w[32];
+  double w[8];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    w[i] = entry(0, i);
-    w[P + i] = entry(1, i);
-  }
+  for (int i = 0; i < 8; ++i) w[i] = entry(q / 2, 8 * (q % 2) + i);
   // earlier reflectors
   for (int bi = 0; bi < j; ++bi) {
-    for (int e = threadIdx.x; e < 32 * P; e += kWave) s_V[e] = RF[(size_t)bi * 32 * P + e];
-    if (threadIdx.x < P) s_tau[threadIdx.x] = TU[bi * P + threadIdx.x];
+    for (int e = lane; e < 32 * P; e += kWave) s_V[e] = RF[(size_t)bi * 32 * P + e];
+    if (lane < P) s_tau[lane] = TU[bi * P + lane];
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < P; ++t) {
       const double tau = s_tau[t];
       if (tau == 0.0) continue;
-      double dot = w[t];
+      double v[8];
+      double d = 0.0;
 #pragma unroll
-      for (int r = t + 1; r < 32; ++r) dot += s_V[r * P + t] * w[r];
-      dot *= tau;
-      w[t] -= dot;
+      for (int i = 0; i < 8; ++i) {
+        const int r = 8 * q + i;
+        v[i] = r > t ? s_V[r * P + t] : (r == t ? 1.0 : 0.0);
+        d += v[i] * w[i];
+      }
+      d = quad_sum(d) * tau;
 #pragma unroll
-      for (int r = t + 1; r < 32; ++r) w[r] -= dot * s_V[r * P + t];
+      for (int i = 0; i < 8; ++i) w[i] -= d * v[i];
     }
     __syncthreads();  // s_V is overwritten next
-    if (own) {
+    if (q < 2) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) hcol[16 * bi + i] = w[i];
+      for (int i = 0; i < 8; ++i) hcol[16 * bi + 8 * q + i] = w[i];
     }
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      w[i] = w[P + i];
-      w[P + i] = entry(bi + 2, i);
+    for (int i = 0; i < 8; ++i) {
+      const double up = __shfl(w[i], lane + 2, kWave);
+      w[i] = q < 2 ? up : entry(bi + 2, 8 * (q % 2) + i);
     }
   }
   // new reflectors on the panel rows 16 j .. 16 j + 31
-  double g[32];
+  double g[8];
 #pragma unroll
-  for (int r = 0; r < 32; ++r) g[r] = G[(size_t)(16 * j + r) * P + cc];
+  for (int i = 0; i < 8; ++i) g[i] = G[(size_t)(16 * j + 8 * q + i) * P + col];
   double* Vn = RF + (size_t)j * 32 * P;
 #pragma unroll
   for (int t = 0; t < P; ++t) {
-    if (c == t) {
-      const double alpha = w[t];
-      double xn2 = 0.0;
+    // every quad forms the reflector of its own column; quad t's is the one used
+    double xn2 = 0.0;
 #pragma unroll
-      for (int r = t + 1; r < 32; ++r) xn2 += w[r] * w[r];
+    for (int i = 0; i < 8; ++i)
+      if (8 * q + i > t) xn2 += w[i] * w[i];
+    xn2 = quad_sum(xn2);
+    const double alpha = quad_sum(q == t / 8 ? w[t % 8] : 0.0);
+    if (col == t) {
       double tau = 0.0;
       double beta = alpha;
+      double sc = 0.0;
       if (xn2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
         tau = (beta - alpha) / beta;
-        const double sc = 1.0 / (alpha - beta);
+        sc = 1.0 / (alpha - beta);
+      }
 #pragma unroll
-        for (int r = t + 1; r < 32; ++r) {
-          const double v = w[r] * sc;
+      for (int i = 0; i < 8; ++i) {
+        const int r = 8 * q + i;
+        if (r > t) {
+          const double v = w[i] * sc;
           s_v[r] = v;
           Vn[r * P + t] = v;
-          w[r] = 0.0;
-        }
-      } else {
-#pragma unroll
-        for (int r = t + 1; r < 32; ++r) {
-          s_v[r] = 0.0;
-          Vn[r * P + t] = 0.0;
+          w[i] = 0.0;
         }
       }
-      w[t] = beta;
-      s_t = tau;
-      TU[j * P + t] = tau;
+      if (q == t / 8) w[t % 8] = beta;
+      if (q == 0) {
+        s_t = tau;
+        TU[j * P + t] = tau;
+      }
     }
     __syncthreads();
     const double tau = s_t;
-    if (tau != 0.0 && own) {
-      if (c > t) {
-        double dot = w[t];
+    if (tau != 0.0) {
+      double v[8];
 #pragma unroll
-        for (int r = t + 1; r < 32; ++r) dot += s_v[r] * w[r];
-        dot *= tau;
-        w[t] -= dot;
-#pragma unroll
-        for (int r = t + 1; r < 32; ++r) w[r] -= dot * s_v[r];
+      for (int i = 0; i < 8; ++i) {
+        const int r = 8 * q + i;
+        v[i] = r > t ? s_v[r] : (r == t ? 1.0 : 0.0);
       }
-      double dot = g[t];
+      if (col > t) {
+        double d = 0.0;
 #pragma unroll
-      for (int r = t + 1; r < 32; ++r) dot += s_v[r] * g[r];
-      dot *= tau;
-      g[t] -= dot;
+        for (int i = 0; i < 8; ++i) d += v[i] * w[i];
+        d = quad_sum(d) * tau;
 #pragma unroll
-      for (int r = t + 1; r < 32; ++r) g[r] -= dot * s_v[r];
+        for (int i = 0; i < 8; ++i) w[i] -= d * v[i];
+      }
+      double d = 0.0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) d += v[i] * g[i];
+      d = quad_sum(d) * tau;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) g[i] -= d * v[i];
     }
     __syncthreads();
   }
-  if (own) {
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
-      hcol[16 * j + r] = w[r];
-      G[(size_t)(16 * j + r) * P + c] = g[r];
-    }
-    for (int i = 16 * (j + 2); i < ldh; ++i) hcol[i] = 0.0;
+  for (int i = 0; i < 8; ++i) {
+    hcol[16 * j + 8 * q + i] = w[i];
+    G[(size_t)(16 * j + 8 * q + i) * P + col] = g[i];
   }
-  if (c == 0) {
+  for (int i = 16 * (j + 2) + q; i < ldh; i += 4) hcol[i] = 0.0;
+  if (lane == 0) {
     st[s].kblk = j + 1;
     if (st[s].brk) {
       st[s].cycle_done = 1;
@@ -712,8 +726,12 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
   }
 }
 
-// Y = R^{-1} G over the K = 16 kblk leading rows (column-oriented
-// back-substitution), rounded into Yf[s][b][i * 16 + c] (row 16 b + i).
+// Y = R^{-1} G over the K = 16 kblk leading rows, rounded into
+// Yf[s][b][i * 16 + c] (row 16 b + i).  Block back-substitution from the
+// bottom: the 16 x 16 diagonal block of R and the 16 right-hand-side rows are
+// solved in LDS (column-oriented), then the rows above are updated with that
+// block's 16 solution rows.  Every G row receives its subtractions in the
+// order of decreasing solution row, as in the row-by-row column-oriented form.
 template <class T>
 __global__ __launch_bounds__(kBlock) void bbacksolve_kernel(const BState* __restrict__ st,
                                                             const double* __restrict__ Hq,
@@ -723,21 +741,33 @@ __global__ __launch_bounds__(kBlock) void bbacksolve_kernel(const BState* __rest
   const int s = blockIdx.x;
   const BState ss = st[s];
   if (!ss.active || ss.kblk <= 0) return;
-  const int K = 16 * ss.kblk;
-  const double* H = Hq + (size_t)s * hstride;
+  __shared__ double sR[PP];  // sR[k][i] = R[16 b + k][16 b + i]
+  __shared__ double sG[PP];  // the block's 16 rows of G, then of Y
+  const double* H = Hq + (size_t)s * hstride;  // column-major, H[col * ldh + row]
   double* G = Grhs + (size_t)s * gstride;
   T* Y = Yf + (size_t)s * ystride;
-  const int c = threadIdx.x % P;
-  const int rg = threadIdx.x / P;
-  for (int i = K - 1; i >= 0; --i) {
-    if (threadIdx.x < P) {
-      const double y = G[(size_t)i * P + c] / H[(size_t)i * ldh + i];
-      G[(size_t)i * P + c] = y;
-      Y[(size_t)i * P + c] = T(y);
-    }
+  const int e = threadIdx.x;
+  const int ei = e / P;  // row within the block
+  const int c = e % P;   // right-hand side
+  for (int b = ss.kblk - 1; b >= 0; --b) {
+    const int r0 = 16 * b;
+    sR[ei * P + c] = H[(size_t)(r0 + c) * ldh + r0 + ei];
+    sG[e] = G[(size_t)(r0 + ei) * P + c];
     __syncthreads();
-    const double y = G[(size_t)i * P + c];
-    for (int r = rg; r < i; r += kBlock / P) G[(size_t)r * P + c] -= H[(size_t)i * ldh + r] * y;
+    for (int i = P - 1; i >= 0; --i) {
+      if (ei == i) sG[e] = sG[e] / sR[i * P + i];
+      __syncthreads();
+      if (ei < i) sG[e] -= sR[ei * P + i] * sG[i * P + c];
+      __syncthreads();
+    }
+    G[(size_t)(r0 + ei) * P + c] = sG[e];
+    Y[(size_t)(r0 + ei) * P + c] = T(sG[e]);
+    // rows above the block: G[r] -= sum over the block's rows i (decreasing) of R[r][i] y_i
+    for (int r = ei; r < r0; r += kBlock / P) {
+      double g = G[(size_t)r * P + c];
+      for (int i = P - 1; i >= 0; --i) g -= H[(size_t)(r0 + i) * ldh + r] * sG[i * P + c];
+      G[(size_t)r * P + c] = g;
+    }
     __syncthreads();
   }
 }
@@ -761,6 +791,7 @@ struct gmr_batch {
   std::vector<BSys> sys;
   std::vector<BTile> tiles;
   int max_tiles = 0;  // tile count at the smallest tile size (workspace sizing)
+  bool graph = false; // replay each restart cycle as a captured hipGraph
 };
 
 namespace {
@@ -892,18 +923,24 @@ template <class T, int MODE>
 gmr_status gemm_launch(const BRun& R, const T* V, int nblk, const T* Cf, size_t cstride, T* out, double* X64,
                        double tol) {
   const size_t lds = (size_t)nblk * PP * sizeof(T);
-  if (lds > 64 * 1024) {
-    static bool raised = false;  // once per instantiation and process
-    if (!raised) {
-      BH(hipFuncSetAttribute(reinterpret_cast<const void*>(&bgemm_kernel<T, MODE>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxBlocks * PP * sizeof(T))));
-      raised = true;
-    }
-  }
   bgemm_kernel<T, MODE><<<R.ntiles(), kBlock, lds, R.s>>>(R.at<BTile>(R.L.tiles), R.at<BState>(R.L.st), V,
                                                           R.L.vstride, nblk, Cf, cstride, out, X64,
                                                           R.at<double>(R.L.gam), R.at<double>(R.L.bnorm), tol);
   return launch_check("bgemm_kernel");
+}
+
+// Raises the dynamic LDS limit of the block-update kernels to the largest
+// coefficient set (called before any launch, outside graph capture).
+template <class T>
+gmr_status raise_lds_limits() {
+  const int bytes = (int)(kMaxBlocks * PP * sizeof(T));
+  BH(hipFuncSetAttribute(reinterpret_cast<const void*>(&bgemm_kernel<T, kSub>),
+                         hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  BH(hipFuncSetAttribute(reinterpret_cast<const void*>(&bgemm_kernel<T, kSet>),
+                         hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  BH(hipFuncSetAttribute(reinterpret_cast<const void*>(&bgemm_kernel<T, kXupd>),
+                         hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  return GMR_OK;
 }
 
 template <class T, int MODE>
@@ -935,6 +972,24 @@ gmr_status cholqr2(const BRun& R, T* Tm, T* dst, double tau, bool start) {
   BT(dots<T>(R, Tm, 1, Tm, Cd, nullptr));
   BT(chol<T>(R, Cd, start ? nullptr : R.at<double>(R.L.R1), start ? nullptr : R.at<double>(R.L.Rn), tau, m2));
   return gemm<T, kSet>(R, Tm, 1, Cf, dst);
+}
+
+// Captures what `body` enqueues on stream s into an executable graph.
+template <class F>
+gmr_status capture_graph(hipStream_t s, hipGraphExec_t* out, F&& body) {
+  BH(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const gmr_status st = body();
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != GMR_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return gmr::fail(GMR_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return gmr::fail(GMR_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  return GMR_OK;
 }
 
 gmr_status check_batch_csr(const gmr_csr* A, int dtype, int64_t rows) {
@@ -994,6 +1049,12 @@ gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_block
   return GMR_OK;
 }
 
+gmr_status batch_set_graph(gmr_batch* b, int32_t on) {
+  if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_set_graph: null batch");
+  b->graph = on != 0;
+  return GMR_OK;
+}
+
 gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* group_blocks) {
   if (!b || !tile_rows || !group_blocks) return gmr::fail(GMR_ERR_INVALID, "batch_get_tiling: null pointer");
   *tile_rows = b->tile_rows;
@@ -1027,6 +1088,13 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
   BT(check_batch_csr(Ain, sizeof(T) == 8 ? GMR_F64 : GMR_F32, b->rows));
   BRun R{b, layout(b, sizeof(T)), (char*)ws, (hipStream_t)stream};
   if (!ws || ws_bytes < R.L.end) return gmr::fail(GMR_ERR_WORKSPACE, nm + ": workspace too small");
+  BT(raise_lds_limits<T>());
+  if (b->graph) {
+    // capture needs a stream other than the legacy one: the solve runs on the
+    // library's own stream once the caller's stream has drained
+    BH(hipStreamSynchronize(R.s));
+    BT(library_stream(&R.s));
+  }
   const int ns = b->nsys;
   const int m = b->m;
   const int nt = R.ntiles();
@@ -1062,34 +1130,10 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
     return launch_check("bfinish_res_kernel");
   };
   BT(residual());
-  std::vector<int> cycles(ns, 0);
-  int total_cycles = 0;
-  int64_t block_iters = 0;
-  gmr_status status = GMR_NOT_CONVERGED;
-  for (int cyc = 0;; ++cyc) {
-    BH(hipMemcpyAsync(hst.data(), st, ns * sizeof(BState), hipMemcpyDeviceToHost, R.s));
-    BH(hipStreamSynchronize(R.s));
-    int active = 0, failed = 0;
-    for (int s = 0; s < ns; ++s) {
-      if (hst[s].failed) ++failed;
-      else if (hst[s].active) ++active;
-    }
-    if (cyc > 0)
-      for (int s = 0; s < ns; ++s)
-        if (hst[s].kblk > 0) block_iters += hst[s].kblk;
-    if (failed) {
-      status = GMR_ERR_NONFINITE;
-      gmr::fail(GMR_ERR_NONFINITE, nm + ": a start block could not be orthonormalised");
-      break;
-    }
-    if (active == 0) {
-      status = GMR_OK;
-      break;
-    }
-    if (cyc >= max_cycles) break;
-    for (int s = 0; s < ns; ++s)
-      if (hst[s].active) ++cycles[s];
-    ++total_cycles;
+  // Everything one restart cycle enqueues, from the start block to the next
+  // residual; the same launches with the same arguments every cycle, so it
+  // can be captured once and replayed.
+  auto enqueue_cycle = [&]() -> gmr_status {
     // --- start block: W = R/gamma, dependent columns from Z, Cholesky QR twice
     bcycle_reset_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, st);
     bstart_kernel<T><<<nt, kBlock, 0, R.s>>>(tl, st, R64, gam, W);
@@ -1126,7 +1170,48 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
     BT(launch_check("bbacksolve_kernel"));
     // the update reads C from Yf, laid out like the Gram-Schmidt coefficients
     BT((gemm_launch<T, kXupd>(R, V, m, Yf, R.L.ystride, nullptr, X, tol)));
-    BT(residual());
+    return residual();
+  };
+  struct GraphExec {
+    hipGraphExec_t g = nullptr;
+    ~GraphExec() {
+      if (g) (void)hipGraphExecDestroy(g);
+    }
+  } graph;
+  std::vector<int> cycles(ns, 0);
+  int total_cycles = 0;
+  int64_t block_iters = 0;
+  gmr_status status = GMR_NOT_CONVERGED;
+  for (int cyc = 0;; ++cyc) {
+    BH(hipMemcpyAsync(hst.data(), st, ns * sizeof(BState), hipMemcpyDeviceToHost, R.s));
+    BH(hipStreamSynchronize(R.s));
+    int active = 0, failed = 0;
+    for (int s = 0; s < ns; ++s) {
+      if (hst[s].failed) ++failed;
+      else if (hst[s].active) ++active;
+    }
+    if (cyc > 0)
+      for (int s = 0; s < ns; ++s)
+        if (hst[s].kblk > 0) block_iters += hst[s].kblk;
+    if (failed) {
+      status = GMR_ERR_NONFINITE;
+      gmr::fail(GMR_ERR_NONFINITE, nm + ": a start block could not be orthonormalised");
+      break;
+    }
+    if (active == 0) {
+      status = GMR_OK;
+      break;
+    }
+    if (cyc >= max_cycles) break;
+    for (int s = 0; s < ns; ++s)
+      if (hst[s].active) ++cycles[s];
+    ++total_cycles;
+    if (b->graph) {
+      if (!graph.g) BT(capture_graph(R.s, &graph.g, enqueue_cycle));
+      BH(hipGraphLaunch(graph.g, R.s));
+    } else {
+      BT(enqueue_cycle());
+    }
   }
   BH(hipStreamSynchronize(R.s));
   std::vector<double> hg(ns * P), hb(ns * P);

@@ -241,8 +241,11 @@ static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, con
   return check_launch("finish_cols_kernel");
 }
 
-// Largest j for which the update and the second dots fuse (basis row in registers).
-template <class T> constexpr int fused_max() { return sizeof(T) == 4 ? 128 : 64; }
+// Largest j for which the update and the second dots fuse (basis row in
+// registers).  Beyond 64 columns the register footprint drops the fused
+// kernel to one wave per SIMD, and the separate update and dots passes are
+// faster although they read V twice.
+template <class T> constexpr int fused_max() { return 64; }
 
 template <class T>
 static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* hin,
@@ -262,10 +265,7 @@ static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t l
   if (j <= 8) GMR_UD(8);
   else if (j <= 16) GMR_UD(16);
   else if (j <= 32) GMR_UD(32);
-  else if (j <= 64) GMR_UD(64);
-  else {
-    if constexpr (sizeof(T) == 4) GMR_UD(128);
-  }
+  else GMR_UD(64);
 #undef GMR_UD
   GMR_TRY(check_launch("cgs_update_dots_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, (double)(j + 2) * n * sizeof(T)));
@@ -427,7 +427,7 @@ struct CycleGraph {
   template <class F>
   gmr_status capture(hipStream_t s, F&& body) {
     if (exec) {
-      hipGraphExecDestroy(exec);
+      (void)hipGraphExecDestroy(exec);
       exec = nullptr;
     }
     GMR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -435,22 +435,21 @@ struct CycleGraph {
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s, &g);
     if (st != GMR_OK) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return st;
     }
     if (e != hipSuccess) return fail(GMR_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     const hipError_t e2 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e2 != hipSuccess) return fail(GMR_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
     return GMR_OK;
   }
   ~CycleGraph() {
-    if (exec) hipGraphExecDestroy(exec);
+    if (exec) (void)hipGraphExecDestroy(exec);
   }
 };
 
-// A non-blocking stream of default priority per device, created on first use.
-static gmr_status library_stream(hipStream_t* out) {
+gmr_status library_stream(hipStream_t* out) {
   static thread_local hipStream_t streams[64] = {};
   int dev = 0;
   GMR_HIP(hipGetDevice(&dev));
@@ -482,6 +481,11 @@ static gmr_status solve_impl(const SolveArgs& a) {
     GMR_HIP(hipStreamSynchronize(a.stream));
     GMR_TRY(library_stream(&c.s));
   }
+  // one block per cycle for a small system without a polynomial (profiling
+  // and graph replay keep the multi-kernel cycle)
+  const bool persistent = (prm.flags & GMR_FLAG_PERSISTENT) && n <= kSmallMaxN && !poly && !graph.use &&
+                          prm.prof_kernel == GMR_PROF_NONE;
+  const double brk_thresh = sizeof(TI) == 4 ? 1e3 * 1.1754943508222875e-38 : 0.0;
   Prof& pf = prof_state();
   pf.family = prm.prof_kernel;
   pf.used = 0;
@@ -600,6 +604,12 @@ static gmr_status solve_impl(const SolveArgs& a) {
         graph.mc = mc;
       }
       GMR_HIP(hipGraphLaunch(graph.exec, c.s));
+    } else if (persistent) {
+      small_cycle_kernel<TI, TO><<<1, kBlock, 0, c.s>>>(
+          n, a.Ain->row_ptr, a.Ain->col_idx, (const TI*)a.Ain->val, a.Aout->row_ptr, a.Aout->col_idx,
+          (const TO*)a.Aout->val, b, x, r, V, B.ldv, W[0], W[1], cs, ws.partial(), ws.h1t<TI>(),
+          ws.h2t<TI>(), mc, implicit_stop ? prm.tol * bnorm : -1.0, brk_thresh);
+      GMR_TRY(check_launch("small_cycle_kernel"));
     } else {
       GMR_TRY(enqueue_cycle(mc));
       GMR_TRY(residual());

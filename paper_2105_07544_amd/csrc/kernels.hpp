@@ -254,9 +254,9 @@ __global__ __launch_bounds__(kBlock) void finish_norm2_kernel(int nparts, const 
 // Start of a cycle: w = cast(r * (1/gamma)) into the inner precision with the
 // block's partial ||w||^2 accumulated in the inner precision.
 template <class TO, class TI>
-__global__ __launch_bounds__(kBlock) void start_cycle_kernel(int n, const TO* __restrict__ r,
-                                                             TI* __restrict__ w, double* partial,
-                                                             const Status* __restrict__ st) {
+__device__ __forceinline__ void start_cycle_body(int n, const TO* __restrict__ r,
+                                                 TI* __restrict__ w, double* partial,
+                                                 const Status* __restrict__ st) {
   const TO ig = TO(st->inv_gamma);
   TI sq = TI(0);
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -268,11 +268,18 @@ __global__ __launch_bounds__(kBlock) void start_cycle_kernel(int n, const TO* __
   if (threadIdx.x == 0) partial[blockIdx.x] = double(sq);
 }
 
+template <class TO, class TI>
+__global__ __launch_bounds__(kBlock) void start_cycle_kernel(int n, const TO* __restrict__ r,
+                                                             TI* __restrict__ w, double* partial,
+                                                             const Status* __restrict__ st) {
+  start_cycle_body<TO, TI>(n, r, w, partial, st);
+}
+
 // beta0 = ||w|| (rounded to the inner precision), g = beta0 e1, cycle flags reset.
 // `stop_rel` >= 0 arms the implicit residual test |g_{j+1}| * gamma <= stop_rel.
 template <class TI>
-__global__ __launch_bounds__(kBlock) void finish_start_cycle_kernel(int nparts, const double* partial,
-                                                                    CycleState cs, double stop_rel) {
+__device__ __forceinline__ void finish_start_cycle_body(int nparts, const double* partial,
+                                                        CycleState cs, double stop_rel) {
   const double s = sum_partials(nparts, partial);
   if (threadIdx.x == 0) {
     const double b0 = sqrt(double(TI(s)));
@@ -287,6 +294,12 @@ __global__ __launch_bounds__(kBlock) void finish_start_cycle_kernel(int nparts, 
     st->res = b0;
     st->stop_thresh = (stop_rel >= 0.0) ? stop_rel * st->inv_gamma : -1.0;
   }
+}
+
+template <class TI>
+__global__ __launch_bounds__(kBlock) void finish_start_cycle_kernel(int nparts, const double* partial,
+                                                                    CycleState cs, double stop_rel) {
+  finish_start_cycle_body<TI>(nparts, partial, cs, stop_rel);
 }
 
 // ===========================================================================
@@ -343,10 +356,10 @@ __global__ __launch_bounds__(kBlock) void finish_cols_kernel(int nparts, const d
 
 // Pass 1: h = V_j^T w  (j <= NQ * K columns, in NQ chunks of K columns).
 template <class T, int K, int NQ>
-__global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T* __restrict__ V,
-                                                          int64_t ldv, const T* __restrict__ w,
-                                                          double* partial,
-                                                          const int* __restrict__ done) {
+__device__ __forceinline__ void cgs_dots_body(int n, int j, const T* __restrict__ V,
+                                              int64_t ldv, const T* __restrict__ w,
+                                              double* partial,
+                                              const int* __restrict__ done) {
   constexpr int KO = Butterfly<K>::KOut;
   if (done && *done) return;
   const int lane = threadIdx.x % kWave;
@@ -382,11 +395,19 @@ __global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T*
   publish_col_partials<K, T, NQ>(acc, j, partial);
 }
 
+template <class T, int K, int NQ>
+__global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T* __restrict__ V,
+                                                          int64_t ldv, const T* __restrict__ w,
+                                                          double* partial,
+                                                          const int* __restrict__ done) {
+  cgs_dots_body<T, K, NQ>(n, j, V, ldv, w, partial, done);
+}
+
 // Pass-1 update fused with pass-2 dots: w -= V_j h_in ; h_out = V_j^T w.
 // The j basis entries of a row stay in registers between the two uses, so V
 // is read once.  Needs j <= K.
 template <class T, int K>
-__global__ __launch_bounds__(kBlock) void cgs_update_dots_kernel(
+__device__ __forceinline__ void cgs_update_dots_body(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
     T* __restrict__ w, double* partial, const int* __restrict__ done) {
   constexpr int KO = Butterfly<K>::KOut;
@@ -420,12 +441,19 @@ __global__ __launch_bounds__(kBlock) void cgs_update_dots_kernel(
   publish_col_partials<K, T, 1>(acc, j, partial);
 }
 
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void cgs_update_dots_kernel(
+    int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
+    T* __restrict__ w, double* partial, const int* __restrict__ done) {
+  cgs_update_dots_body<T, K>(n, j, V, ldv, h_in, w, partial, done);
+}
+
 // Plain update w -= V_j h_in (used when j is too large to fuse).
 template <class T>
-__global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const T* __restrict__ V,
-                                                            int64_t ldv, const T* __restrict__ h_in,
-                                                            T* __restrict__ w,
-                                                            const int* __restrict__ done) {
+__device__ __forceinline__ void cgs_update_body(int n, int j, const T* __restrict__ V,
+                                                int64_t ldv, const T* __restrict__ h_in,
+                                                T* __restrict__ w,
+                                                const int* __restrict__ done) {
   __shared__ T s_h[kMaxCols];
   if (done && *done) return;
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
@@ -443,6 +471,14 @@ __global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const 
     for (; c < j; ++c) wv -= V[(size_t)c * ldv + r] * s_h[c];
     w[r] = wv;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const T* __restrict__ V,
+                                                            int64_t ldv, const T* __restrict__ h_in,
+                                                            T* __restrict__ w,
+                                                            const int* __restrict__ done) {
+  cgs_update_body<T>(n, j, V, ldv, h_in, w, done);
 }
 
 // ---------------------------------------------------------------------------
@@ -545,7 +581,7 @@ __device__ __forceinline__ void givens_tail(CycleState cs, int jc, int last_jc, 
 // Pass-2 update and norm: w -= V_j h_in with the block's partial ||w||^2
 // accumulated in the working precision.
 template <class T>
-__global__ __launch_bounds__(kBlock) void cgs_update_norm_kernel(
+__device__ __forceinline__ void cgs_update_norm_body(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
     T* __restrict__ w, double* partial, const int* __restrict__ done) {
   __shared__ T s_h[kMaxCols];
@@ -571,13 +607,20 @@ __global__ __launch_bounds__(kBlock) void cgs_update_norm_kernel(
   if (threadIdx.x == 0) partial[blockIdx.x] = double(sq);
 }
 
+template <class T>
+__global__ __launch_bounds__(kBlock) void cgs_update_norm_kernel(
+    int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
+    T* __restrict__ w, double* partial, const int* __restrict__ done) {
+  cgs_update_norm_body<T>(n, j, V, ldv, h_in, w, partial, done);
+}
+
 // beta = ||w|| from the partials, then the tail: the Givens step (solver) or
 // h = h1 + h2, beta (standalone CGS2).
 template <class T, int MODE>
-__global__ __launch_bounds__(kBlock) void finish_norm_kernel(int nparts, const double* partial,
-                                                             CycleState cs, int j, int last_jc,
-                                                             double breakdown_thresh, double* hout,
-                                                             const int* __restrict__ done) {
+__device__ __forceinline__ void finish_norm_body(int nparts, const double* partial,
+                                                 CycleState cs, int j, int last_jc,
+                                                 double breakdown_thresh, double* hout,
+                                                 const int* __restrict__ done) {
   if (done && *done) return;
   const double s = sum_partials(nparts, partial);
   // beta in the working precision, as the float32 inner solver would have it
@@ -589,6 +632,14 @@ __global__ __launch_bounds__(kBlock) void finish_norm_kernel(int nparts, const d
     for (int c = threadIdx.x; c < j; c += kBlock) hout[c] = cs.h1d[c] + cs.h2d[c];
     if (threadIdx.x == 0) hout[j] = beta;
   }
+}
+
+template <class T, int MODE>
+__global__ __launch_bounds__(kBlock) void finish_norm_kernel(int nparts, const double* partial,
+                                                             CycleState cs, int j, int last_jc,
+                                                             double breakdown_thresh, double* hout,
+                                                             const int* __restrict__ done) {
+  finish_norm_body<T, MODE>(nparts, partial, cs, j, last_jc, breakdown_thresh, hout, done);
 }
 
 // ===========================================================================
@@ -607,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void scale_kernel(int n, const T* __restric
 // u = V[:, 0:k] y in the working precision (k read from the status), then,
 // when x is given, x += gamma * (TO) u; otherwise u is stored.
 template <class TI, class TO>
-__global__ __launch_bounds__(kBlock) void solution_update_kernel(
+__device__ __forceinline__ void solution_update_body(
     int n, const TI* __restrict__ V, int64_t ldv, const double* __restrict__ y,
     const Status* __restrict__ st, TI* __restrict__ u, TO* __restrict__ x) {
   __shared__ TI s_y[kMaxCols];
@@ -621,6 +672,13 @@ __global__ __launch_bounds__(kBlock) void solution_update_kernel(
     if (x) x[r] += gam * TO(s);
     else u[r] = s;
   }
+}
+
+template <class TI, class TO>
+__global__ __launch_bounds__(kBlock) void solution_update_kernel(
+    int n, const TI* __restrict__ V, int64_t ldv, const double* __restrict__ y,
+    const Status* __restrict__ st, TI* __restrict__ u, TO* __restrict__ x) {
+  solution_update_body<TI, TO>(n, V, ldv, y, st, u, x);
 }
 
 // x += gamma * (TO) u
@@ -719,6 +777,122 @@ __global__ __launch_bounds__(kBlock) void poly_pair2_kernel(int n, const int* __
   const int r = r0 + threadIdx.x;
   const T at = spmv_row<T, false>(n, r0, rp, ci, val, Tt, T(1), s_prod, s_rp);
   if (r < n) Pn[r] = P[r] - (c1 * Tt[r] - c2 * at);
+}
+
+// ===========================================================================
+// Persistent single-block cycle for small systems
+// ===========================================================================
+// Largest n run as one block per cycle: beyond it the block walks too many
+// 256-row SpMV chunks and the multi-block cycle is faster.
+constexpr int kSmallMaxN = 32768;
+
+// Column sums of the single block's CGS partials: out = partial[c][0].
+template <class T>
+__device__ __forceinline__ void take_cols(int j, const double* __restrict__ partial, double* out,
+                                          T* outT) {
+  for (int c = threadIdx.x; c < j; c += kBlock) {
+    const double s = partial[(size_t)c * kPartPitch];
+    out[c] = s;
+    outT[c] = T(s);
+  }
+}
+
+// The three CGS2 passes on w against the j columns of V, the update+dots pass
+// fused up to 64 columns, as the multi-kernel path does.
+template <class T>
+__device__ __forceinline__ void small_cgs2(int n, int j, const T* V, int64_t ldv, T* w, double* partial,
+                                           CycleState cs, T* h1t, T* h2t, int last_jc, double thresh) {
+  if (j <= 8) cgs_dots_body<T, 8, 1>(n, j, V, ldv, w, partial, nullptr);
+  else if (j <= 16) cgs_dots_body<T, 16, 1>(n, j, V, ldv, w, partial, nullptr);
+  else if (j <= 32) cgs_dots_body<T, 32, 1>(n, j, V, ldv, w, partial, nullptr);
+  else if (j <= 64) cgs_dots_body<T, 64, 1>(n, j, V, ldv, w, partial, nullptr);
+  else cgs_dots_body<T, 64, 4>(n, j, V, ldv, w, partial, nullptr);
+  __syncthreads();
+  take_cols<T>(j, partial, cs.h1d, h1t);
+  __syncthreads();
+  if (j <= 8) cgs_update_dots_body<T, 8>(n, j, V, ldv, h1t, w, partial, nullptr);
+  else if (j <= 16) cgs_update_dots_body<T, 16>(n, j, V, ldv, h1t, w, partial, nullptr);
+  else if (j <= 32) cgs_update_dots_body<T, 32>(n, j, V, ldv, h1t, w, partial, nullptr);
+  else if (j <= 64) cgs_update_dots_body<T, 64>(n, j, V, ldv, h1t, w, partial, nullptr);
+  else {
+    cgs_update_body<T>(n, j, V, ldv, h1t, w, nullptr);
+    __syncthreads();
+    cgs_dots_body<T, 64, 4>(n, j, V, ldv, w, partial, nullptr);
+  }
+  __syncthreads();
+  take_cols<T>(j, partial, cs.h2d, h2t);
+  __syncthreads();
+  cgs_update_norm_body<T>(n, j, V, ldv, h2t, w, partial, nullptr);
+  __syncthreads();
+  finish_norm_body<T, kTailGivens>(1, partial, cs, j, last_jc, thresh, nullptr, nullptr);
+  __syncthreads();
+}
+
+// One whole restart cycle in one block of 256 threads: the cast of r, up to
+// mc inner iterations (SpMV with the fused normalisation, CGS2, the float64
+// Givens step), the solution update and the next residual with its norm.  The
+// device steps are those of the multi-kernel cycle, with block barriers where
+// that path has kernel boundaries; for a small system this replaces some 8
+// launches per iteration by one launch per cycle.  Launched as <<<1, kBlock>>>.
+template <class TI, class TO>
+__global__ __launch_bounds__(kBlock) void small_cycle_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const TI* __restrict__ vin,
+    const int* __restrict__ rpo, const int* __restrict__ cio, const TO* __restrict__ vout,
+    const TO* __restrict__ b, TO* __restrict__ x, TO* __restrict__ r, TI* V,
+    int64_t ldv, TI* w0, TI* w1, CycleState cs, double* partial, TI* h1t, TI* h2t, int mc, double stop_rel,
+    double thresh) {
+  __shared__ TI s_pi[kSpmvChunk];
+  __shared__ TO s_po[kSpmvChunk];
+  __shared__ int s_rp[kSpmvRows + 1];
+  Status* st = cs.st;
+  start_cycle_body<TO, TI>(n, r, w0, partial, st);
+  __syncthreads();
+  finish_start_cycle_body<TI>(1, partial, cs, stop_rel);
+  __syncthreads();
+  TI* wc = w0;  // the current w (the unnormalised v_j)
+  TI* wn = w1;  // A v_j
+  __shared__ int s_done;
+  for (int j = 0; j < mc; ++j) {
+    // implicit convergence or breakdown: one thread reads the flag and the
+    // block takes the same branch
+    if (threadIdx.x == 0) s_done = st->done;
+    __syncthreads();
+    if (s_done) break;
+    TI* vj = V + (size_t)j * ldv;
+    const TI s = TI(*cs.inv_beta);
+    for (int r0 = 0; r0 < n; r0 += kSpmvRows) {
+      const TI acc = spmv_row<TI, true>(n, r0, rp, ci, vin, wc, s, s_pi, s_rp);
+      const int row = r0 + threadIdx.x;
+      if (row < n) {
+        vj[row] = wc[row] * s;
+        wn[row] = acc;
+      }
+      __syncthreads();  // s_rp is reloaded by the next chunk
+    }
+    small_cgs2<TI>(n, j + 1, V, ldv, wn, partial, cs, h1t, h2t, mc - 1, thresh);
+    TI* t = wc;
+    wc = wn;
+    wn = t;
+  }
+  solution_update_body<TI, TO>(n, V, ldv, cs.y, st, nullptr, x);
+  __syncthreads();
+  double sq = 0.0;
+  for (int r0 = 0; r0 < n; r0 += kSpmvRows) {
+    const TO acc = spmv_row<TO, false>(n, r0, rpo, cio, vout, x, TO(1), s_po, s_rp);
+    const int row = r0 + threadIdx.x;
+    if (row < n) {
+      const TO rv = b[row] - acc;
+      r[row] = rv;
+      sq += double(rv) * double(rv);
+    }
+    __syncthreads();
+  }
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) {
+    const double g = sqrt(sq);
+    st->gamma = g;
+    st->inv_gamma = 1.0 / g;
+  }
 }
 
 }  // namespace gmr

@@ -126,6 +126,33 @@ def test_float64_workspace_too_small_is_an_error():
         b.solve(A64, None, Bd, torch.zeros_like(Bd), torch.from_numpy(Z.astype(np.float32)).to(DEV), ws)
 
 
+@pytest.mark.parametrize("inner", ["f32", "f64"])
+def test_graph_replay_matches_eager(inner):
+    systems = W.config4_batch(count=5, nrhs=16, side_lo=12, side_hi=40, seed=18)
+    A, B, Z, A64, A32 = batch_inputs(systems)
+    b = G.Batch([s["A"].n for s in systems], restart=6)
+    code = G.GMR_F32 if inner == "f32" else G.GMR_F64
+    ws = G.alloc_workspace(b.workspace_bytes(code), DEV)
+    Bd = torch.from_numpy(B).to(DEV)
+    Zd = torch.from_numpy(Z.astype(np.float32)).to(DEV)
+    Ain = A32 if inner == "f32" else None
+    X0 = torch.zeros_like(Bd)
+    ref = b.solve(A64, Ain, Bd, X0, Zd, ws, tol=1e-10, max_cycles=300)
+    assert ref["status"] == 0
+    Xref = host(X0)
+    b.set_graph(True)
+    for rep in range(3):  # replays of a freshly captured graph, with eager work in between
+        torch.cuda.synchronize()
+        _ = (Bd * 2.0).sum().item()
+        X1 = torch.zeros_like(Bd)
+        out = b.solve(A64, Ain, Bd, X1, Zd, ws, tol=1e-10, max_cycles=300)
+        say("graph", inner, rep, out["status_name"], out["cycles"], out["block_iters"])
+        assert out["status"] == 0 and out["cycles"] == ref["cycles"]
+        assert out["block_iters"] == ref["block_iters"]
+        assert np.array_equal(host(X1), Xref)
+    b.set_graph(False)
+
+
 def test_autotune_picks_a_candidate_and_solves():
     systems = W.config4_batch(count=6, nrhs=16, side_lo=20, side_hi=60, seed=15)
     A, B, Z, A64, A32 = batch_inputs(systems)
