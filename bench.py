@@ -209,7 +209,7 @@ def single_system(args, kind):
     graph = bool(args.graph)
 
     # small systems run each restart cycle as one single-block kernel
-    pers = (args.persistent == 1) or (args.persistent < 0 and kind == "laplace2d")
+    pers = (args.persistent == 1) or (args.persistent < 0 and prob.A.n <= 1024)
 
     def ir(prof="none", g=None):
         x.zero_()
@@ -430,7 +430,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run three plain copies of MIB MiB first (counter scale factor)")
     ap.add_argument("--persistent", type=int, default=-1,
-                    help="one single-block kernel per restart cycle (1), off (0), or -1: on for laplace2d")
+                    help="one single-block kernel per restart cycle (1), off (0), or -1: on for n <= 1024")
     ap.add_argument("--graph", type=int, default=0,
                     help="replay each restart cycle as a hipGraph (no per-kernel events then)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

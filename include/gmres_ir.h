@@ -82,12 +82,13 @@ typedef struct {
  * restart (ignored while profiling).  The solve then runs on a library-owned
  * non-blocking stream after `stream` has drained; results are the same bits. */
 #define GMR_FLAG_GRAPH 1
-/* gmr_params.flags: for a small system (n <= 32768) without a polynomial,
+/* gmr_params.flags: for a small system (n <= 1024) without a polynomial,
  * run each whole restart cycle (cast, inner iterations, update, residual) as
  * one kernel of one block, with block barriers instead of kernel boundaries:
- * one launch per cycle instead of about eight per iteration.  Ignored when it
- * does not apply (larger n, polynomial, profiling, GMR_FLAG_GRAPH); the
- * arithmetic is the same, summed in a different grouping. */
+ * one launch per cycle instead of about eight per iteration (2-4x faster at
+ * n ~ 150, break-even at n ~ 1000).  Ignored when it does not apply (larger n,
+ * polynomial, profiling, GMR_FLAG_GRAPH); the arithmetic is the same, summed
+ * in a different grouping. */
 #define GMR_FLAG_PERSISTENT 2
 
 typedef struct {

@@ -782,9 +782,11 @@ __global__ __launch_bounds__(kBlock) void poly_pair2_kernel(int n, const int* __
 // ===========================================================================
 // Persistent single-block cycle for small systems
 // ===========================================================================
-// Largest n run as one block per cycle: beyond it the block walks too many
-// 256-row SpMV chunks and the multi-block cycle is faster.
-constexpr int kSmallMaxN = 32768;
+// Largest n run as one block per cycle.  Measured on the 2D Laplacian,
+// GMRES(50): the single block is 2-4x faster than the multi-kernel cycle at
+// n = 144, 1.3x at n = 576, even at n = 1024, and 3x slower at n = 4096, where
+// four waves cannot hide the latency of the block's serial SpMV chunks.
+constexpr int kSmallMaxN = 1024;
 
 // Column sums of the single block's CGS partials: out = partial[c][0].
 template <class T>
