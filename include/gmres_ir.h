@@ -243,9 +243,11 @@ gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* gro
  * Results are identical to the eager launches. */
 gmr_status batch_set_graph(gmr_batch* b, int32_t on);
 
-/* Times the block Gram-Schmidt contraction pair for every candidate tiling on
- * the batch's own workspace (its contents are overwritten), keeps the fastest
- * and reports it (best_* may be NULL).  Synchronous. */
+/* Times the block Gram-Schmidt contraction pair (dots and update over m/2
+ * blocks, every system active) for every candidate tiling (tile rows 512,
+ * 1024, 2048, 4096 x group blocks 4, 8, 16) on the batch's own workspace (its
+ * contents are overwritten), keeps the fastest and reports it: *best_ms is
+ * the fastest of five timed repetitions (best_* may be NULL).  Synchronous. */
 gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,
                           int32_t* best_group_blocks, double* best_ms, void* stream);
 

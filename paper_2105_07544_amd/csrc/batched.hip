@@ -1281,8 +1281,10 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
       build_tiles(b, tr);
       b->gb = g;
       if ((status = upload_tables(R)) != GMR_OK) break;
-      float ms = 0.f;
-      for (int rep = 0; rep < 3; ++rep) {  // first repetition warms up
+      // the fastest of five timed repetitions after one warm-up: the minimum is
+      // the least noisy estimate of a launch pair's cost
+      float ms = 1e30f;
+      for (int rep = 0; rep < 6; ++rep) {
         if (hipEventRecord(e0, R.s) != hipSuccess) { status = GMR_ERR_HIP; break; }
         if ((status = dots<float>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd),
                                   R.at<float>(R.L.Cf))) != GMR_OK)
@@ -1293,7 +1295,7 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
         if (hipEventRecord(e1, R.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { status = GMR_ERR_HIP; break; }
         float t = 0.f;
         (void)hipEventElapsedTime(&t, e0, e1);
-        if (rep > 0) ms += t;
+        if (rep > 0) ms = std::min(ms, t);
       }
       if (status != GMR_OK) break;
       if (ms < best) {
@@ -1311,7 +1313,7 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
   if (status != GMR_OK) return gmr::fail(status, "batch_autotune: a timed launch failed");
   if (best_tile_rows) *best_tile_rows = bt;
   if (best_group_blocks) *best_group_blocks = bg;
-  if (best_ms) *best_ms = best / 2.0;
+  if (best_ms) *best_ms = best;
   return GMR_OK;
 }
 
