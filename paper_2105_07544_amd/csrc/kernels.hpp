@@ -448,7 +448,44 @@ __global__ __launch_bounds__(kBlock) void cgs_update_dots_kernel(
   cgs_update_dots_body<T, K>(n, j, V, ldv, h_in, w, partial, done);
 }
 
-// Plain update w -= V_j h_in (used when j is too large to fuse).
+// w[r..r+3] -= sum_c V[c][r..r+3] h[c] over the j columns in ascending c: the
+// four rows of a 16-byte (float) or 32-byte (double) vector load per column.
+// Element by element this is the same arithmetic as the one-row form.
+template <class T>
+__device__ __forceinline__ void update_rows4(int j, const T* __restrict__ V, int64_t ldv,
+                                             const T* __restrict__ s_h, T* __restrict__ w, int r,
+                                             T (&out)[4]) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  v4 wv = *reinterpret_cast<const v4*>(w + r);
+  int c = 0;
+  for (; c + 8 <= j; c += 8) {
+    v4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const v4*>(V + (size_t)(c + u) * ldv + r);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) wv -= v[u] * s_h[c + u];
+  }
+  for (; c < j; ++c) wv -= *reinterpret_cast<const v4*>(V + (size_t)c * ldv + r) * s_h[c];
+  *reinterpret_cast<v4*>(w + r) = wv;
+  out[0] = wv.x;
+  out[1] = wv.y;
+  out[2] = wv.z;
+  out[3] = wv.w;
+}
+
+// The same for one row (the rows past the last multiple of 4).
+template <class T>
+__device__ __forceinline__ T update_row(int j, const T* __restrict__ V, int64_t ldv,
+                                        const T* __restrict__ s_h, T* __restrict__ w, int r) {
+  T wv = w[r];
+  for (int c = 0; c < j; ++c) wv -= V[(size_t)c * ldv + r] * s_h[c];
+  w[r] = wv;
+  return wv;
+}
+
+// Plain update w -= V_j h_in (used when j is too large to fuse).  A thread
+// takes four consecutive rows at a time (V columns are 256-byte aligned, so
+// every 4-row group is one aligned vector load per column).
 template <class T>
 __device__ __forceinline__ void cgs_update_body(int n, int j, const T* __restrict__ V,
                                                 int64_t ldv, const T* __restrict__ h_in,
@@ -458,19 +495,12 @@ __device__ __forceinline__ void cgs_update_body(int n, int j, const T* __restric
   if (done && *done) return;
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
   __syncthreads();
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-    T wv = w[r];
-    int c = 0;
-    for (; c + 8 <= j; c += 8) {
-      T v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(c + u) * ldv + r];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) wv -= v[u] * s_h[c + u];
-    }
-    for (; c < j; ++c) wv -= V[(size_t)c * ldv + r] * s_h[c];
-    w[r] = wv;
-  }
+  const int nq = n / 4;
+  T o[4];
+  for (int q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock)
+    update_rows4<T>(j, V, ldv, s_h, w, 4 * q, o);
+  for (int r = 4 * nq + blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock)
+    update_row<T>(j, V, ldv, s_h, w, r);
 }
 
 template <class T>
@@ -579,7 +609,7 @@ __device__ __forceinline__ void givens_tail(CycleState cs, int jc, int last_jc, 
 }
 
 // Pass-2 update and norm: w -= V_j h_in with the block's partial ||w||^2
-// accumulated in the working precision.
+// accumulated in the working precision; four rows per thread at a time.
 template <class T>
 __device__ __forceinline__ void cgs_update_norm_body(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
@@ -589,18 +619,15 @@ __device__ __forceinline__ void cgs_update_norm_body(
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
   __syncthreads();
   T sq = T(0);
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
-    T wv = w[r];
-    int c = 0;
-    for (; c + 16 <= j; c += 16) {
-      T v[16];
+  const int nq = n / 4;
+  T o[4];
+  for (int q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
+    update_rows4<T>(j, V, ldv, s_h, w, 4 * q, o);
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = V[(size_t)(c + u) * ldv + r];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) wv -= v[u] * s_h[c + u];
-    }
-    for (; c < j; ++c) wv -= V[(size_t)c * ldv + r] * s_h[c];
-    w[r] = wv;
+    for (int i = 0; i < 4; ++i) sq += o[i] * o[i];
+  }
+  for (int r = 4 * nq + blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+    const T wv = update_row<T>(j, V, ldv, s_h, w, r);
     sq += wv * wv;
   }
   sq = block_sum(sq);
