@@ -291,6 +291,57 @@ __global__ __launch_bounds__(kBlock) void bdots_kernel(const BTile* __restrict__
   }
 }
 
+// The same products with the blocks split over the waves instead of the rows:
+// wave w accumulates blocks w*WB .. w*WB+WB-1 (then the next 4*WB) over all
+// rows of the tile, SL 4-row slices per iteration, and writes its 16 x 16
+// results straight from the accumulators to the tile's partials, so there is
+// no cross-wave reduction and no LDS.  The four waves walk the same rows, so
+// the W rows they share are L1 hits after the first.
+template <class T, int WB, int SL>
+__global__ __launch_bounds__(kBlock) void bdots_w_kernel(const BTile* __restrict__ tiles,
+                                                         const BState* __restrict__ st,
+                                                         const T* __restrict__ V, size_t vstride,
+                                                         int nblk, const T* __restrict__ W,
+                                                         T* __restrict__ partial, size_t pstride) {
+  typedef typename Mx<T>::v4 v4;
+  const BTile tl = tiles[blockIdx.x];
+  if (!running(st[tl.sys])) return;
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  const int rsub = lane / P;
+  const int col = lane % P;
+  const int rend = tl.r0 + tl.nr;
+  for (int g0 = wave * WB; g0 < nblk; g0 += kWavesPerBlock * WB) {
+    v4 acc[WB];
+#pragma unroll
+    for (int b = 0; b < WB; ++b) acc[b] = v4{T(0), T(0), T(0), T(0)};
+    for (int r = tl.r0; r < rend; r += 4 * SL) {
+      T bw[SL], a[SL][WB];
+#pragma unroll
+      for (int sl = 0; sl < SL; ++sl) {
+        const int row = r + 4 * sl + rsub;
+        const bool ok = row < rend;
+        bw[sl] = ok ? W[(size_t)row * P + col] : T(0);
+#pragma unroll
+        for (int b = 0; b < WB; ++b)
+          a[sl][b] = (ok && g0 + b < nblk) ? V[(size_t)(g0 + b) * vstride + (size_t)row * P + col] : T(0);
+      }
+#pragma unroll
+      for (int b = 0; b < WB; ++b)
+#pragma unroll
+        for (int sl = 0; sl < SL; ++sl) acc[b] = Mx<T>::mfma(a[sl][b], bw[sl], acc[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < WB; ++b)
+      if (g0 + b < nblk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          partial[(size_t)blockIdx.x * pstride + (size_t)(g0 + b) * PP + Mx<T>::row(rsub, q) * P + col] =
+              acc[b][q];
+      }
+  }
+}
+
 // Per system and block b: the tile partials added in tile order (float64),
 // stored as Cd[s][b][.] and rounded into Cf[s][b][.] (matrix-core operand).
 template <class T>
@@ -809,6 +860,11 @@ namespace {
   } while (0)
 
 constexpr int kMinTileRows = 256;
+// group_blocks codes of the wave-split dots kernel (blocks per wave x row slices)
+constexpr int kDotsW2x8 = 2, kDotsW4x4 = 3, kDotsW4x8 = 5;
+inline bool valid_gb(int g) {
+  return g == 4 || g == 8 || g == 16 || g == kDotsW2x8 || g == kDotsW4x4 || g == kDotsW4x8;
+}
 inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 void build_tiles(gmr_batch* b, int tile_rows) {
@@ -905,11 +961,16 @@ gmr_status dots(const BRun& R, const T* V, int nblk, const T* W, double* Cd, T* 
   const BTile* tl = R.at<BTile>(R.L.tiles);
   const BState* st = R.at<BState>(R.L.st);
   T* part = R.at<T>(R.L.partial);
-  const int gb = (sizeof(T) == 8 && R.b->gb > 8) ? 8 : R.b->gb;
+  const int gb = (sizeof(T) == 8 && R.b->gb == 16) ? 8 : R.b->gb;
+  const int g = R.ntiles();
+  const size_t vs = R.L.vstride, ps = R.L.pstride;
   switch (gb) {
-    case 4: bdots_kernel<T, 4><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
-    case 16: bdots_kernel<T, 16><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
-    default: bdots_kernel<T, 8><<<R.ntiles(), kBlock, 0, R.s>>>(tl, st, V, R.L.vstride, nblk, W, part, R.L.pstride); break;
+    case 4: bdots_kernel<T, 4><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    case 16: bdots_kernel<T, 16><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    case kDotsW2x8: bdots_w_kernel<T, 2, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    case kDotsW4x4: bdots_w_kernel<T, 4, 4><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    case kDotsW4x8: bdots_w_kernel<T, 4, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    default: bdots_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
   }
   BT(launch_check("bdots_kernel"));
   bfinish_c_kernel<T><<<dim3(R.b->nsys, nblk), kBlock, 0, R.s>>>(R.at<BSys>(R.L.sys), st, part, R.L.pstride, Cd,
@@ -1042,8 +1103,9 @@ gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_block
   if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: null batch");
   if (tile_rows < kMinTileRows || tile_rows % 16 != 0)
     return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: tile_rows must be a multiple of 16, >= 256");
-  if (group_blocks != 4 && group_blocks != 8 && group_blocks != 16)
-    return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: group_blocks must be 4, 8 or 16");
+  if (!valid_gb(group_blocks))
+    return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: group_blocks must be 4, 8, 16 (LDS-reduced dots) "
+                                      "or 2, 3, 5 (wave-split dots)");
   build_tiles(b, tile_rows);
   b->gb = group_blocks;
   return GMR_OK;
@@ -1272,7 +1334,7 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
   BH(hipEventCreate(&e1));
   const int nb = std::max(1, b->m / 2);
   const int cand_rows[] = {512, 1024, 2048, 4096};
-  const int cand_gb[] = {4, 8, 16};
+  const int cand_gb[] = {4, 8, 16, kDotsW2x8, kDotsW4x4, kDotsW4x8};
   double best = 1e30;
   int bt = b->tile_rows, bg = b->gb;
   gmr_status status = GMR_OK;
