@@ -314,6 +314,7 @@ def batch(args):
     A32 = A64.to_f32()
     m = args.restart or 50
     bt = G.Batch([s["A"].n for s in systems], restart=m)
+    bt.set_graph(bool(args.graph))
     ws = G.alloc_workspace(bt.workspace_bytes(), dev)
     tiling = bt.autotune(ws)
     log(f"bench: autotuned tiling {tiling}")
@@ -352,6 +353,7 @@ def batch(args):
                                    f"sides, rows={A.n}, nnz={A.nnz}, tol 1e-10 per column",
                        "systems": len(systems), "rhs": 16, "rows": A.n, "nnz": A.nnz, "restart": m},
             "rhs_solved_per_s": round(len(systems) * 16 / t, 2), "tiling": list(tiling[:2]),
+            "graph": bool(args.graph),
             "cycles_slowest_system": out["cycles"], "block_iters": out["block_iters"],
             "max_rel_res": out["max_rel_res"], "sampled_host_rel_res": worst,
             "fp64_batched_s": round(t64, 4), "ir_speedup_vs_fp64": round(t64 / t, 3),

@@ -641,8 +641,8 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
                                                     size_t gstride) {
   const int s = blockIdx.x;
   if (!st[s].active || st[s].cycle_done) return;  // a block column that broke down is kept
-  __shared__ double s_V[32 * P];
-  __shared__ double s_tau[P];
+  __shared__ double s_V[2][32 * P];  // reflectors of one earlier block column, double-buffered
+  __shared__ double s_tau[2][P];
   __shared__ double s_v[32];
   __shared__ double s_t;
   const int lane = threadIdx.x;
@@ -665,28 +665,41 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
   double w[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) w[i] = entry(q / 2, 8 * (q % 2) + i);
-  // earlier reflectors
-  for (int bi = 0; bi < j; ++bi) {
-    for (int e = lane; e < 32 * P; e += kWave) s_V[e] = RF[(size_t)bi * 32 * P + e];
-    if (lane < P) s_tau[lane] = TU[bi * P + lane];
+  // earlier reflectors; block column bi + 1's reflectors and the window rows
+  // that enter next are loaded while block column bi is applied
+  constexpr int kPer = 32 * P / kWave;  // reflector entries per lane
+  if (j > 0) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) s_V[0][lane + kWave * u] = RF[lane + kWave * u];
+    if (lane < P) s_tau[0][lane] = TU[lane];
     __syncthreads();
+  }
+  for (int bi = 0; bi < j; ++bi) {
+    const int cur = bi & 1;
+    double nV[kPer], nT = 0.0, nw[8];
+    if (bi + 1 < j) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) nV[u] = RF[(size_t)(bi + 1) * 32 * P + lane + kWave * u];
+      if (lane < P) nT = TU[(bi + 1) * P + lane];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) nw[i] = q < 2 ? 0.0 : entry(bi + 2, 8 * (q % 2) + i);
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-      const double tau = s_tau[t];
+      const double tau = s_tau[cur][t];
       if (tau == 0.0) continue;
       double v[8];
       double d = 0.0;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int r = 8 * q + i;
-        v[i] = r > t ? s_V[r * P + t] : (r == t ? 1.0 : 0.0);
+        v[i] = r > t ? s_V[cur][r * P + t] : (r == t ? 1.0 : 0.0);
         d += v[i] * w[i];
       }
       d = quad_sum(d) * tau;
 #pragma unroll
       for (int i = 0; i < 8; ++i) w[i] -= d * v[i];
     }
-    __syncthreads();  // s_V is overwritten next
     if (q < 2) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) hcol[16 * bi + 8 * q + i] = w[i];
@@ -694,8 +707,14 @@ __global__ __launch_bounds__(kWave) void bls_kernel(int j, BState* st, const dou
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const double up = __shfl(w[i], lane + 2, kWave);
-      w[i] = q < 2 ? up : entry(bi + 2, 8 * (q % 2) + i);
+      w[i] = q < 2 ? up : nw[i];
     }
+    if (bi + 1 < j) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) s_V[cur ^ 1][lane + kWave * u] = nV[u];
+      if (lane < P) s_tau[cur ^ 1][lane] = nT;
+    }
+    __syncthreads();  // the other buffer is complete; this one is free for block column bi + 2
   }
   // new reflectors on the panel rows 16 j .. 16 j + 31
   double g[8];
@@ -860,6 +879,9 @@ namespace {
   } while (0)
 
 constexpr int kMinTileRows = 256;
+// Tiles wanted per launch (4 blocks on each of the 256 CUs): while the active
+// systems give fewer, their tiles are halved, down to kMinTileRows.
+constexpr int kFillTiles = 1024;
 // group_blocks codes of the wave-split dots kernel (blocks per wave x row slices)
 constexpr int kDotsW2x8 = 2, kDotsW4x4 = 3, kDotsW4x8 = 5;
 inline bool valid_gb(int g) {
@@ -867,8 +889,9 @@ inline bool valid_gb(int g) {
 }
 inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
-void build_tiles(gmr_batch* b, int tile_rows) {
-  b->tile_rows = tile_rows;
+// Tile table over the systems with use[s] set (the others get no tiles), with
+// tiles of tile_rows rows; b->tile_rows (the tuned size) is not changed.
+void fill_tiles(gmr_batch* b, int tile_rows, const std::vector<char>& use) {
   b->tiles.clear();
   b->sys.resize(b->nsys);
   int64_t off = 0;
@@ -877,10 +900,16 @@ void build_tiles(gmr_batch* b, int tile_rows) {
     y.row_off = (int)off;
     y.n = b->sys_rows[s];
     y.tile_start = (int)b->tiles.size();
-    for (int r = 0; r < y.n; r += tile_rows) b->tiles.push_back({s, (int)off + r, std::min(tile_rows, y.n - r), 0});
+    if (use[s])
+      for (int r = 0; r < y.n; r += tile_rows) b->tiles.push_back({s, (int)off + r, std::min(tile_rows, y.n - r), 0});
     y.tile_count = (int)b->tiles.size() - y.tile_start;
     off += y.n;
   }
+}
+
+void build_tiles(gmr_batch* b, int tile_rows) {
+  b->tile_rows = tile_rows;
+  fill_tiles(b, tile_rows, std::vector<char>(b->nsys, 1));
 }
 
 int count_tiles(const gmr_batch* b, int tile_rows) {
@@ -1159,7 +1188,8 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
   }
   const int ns = b->nsys;
   const int m = b->m;
-  const int nt = R.ntiles();
+  fill_tiles(b, b->tile_rows, std::vector<char>(ns, 1));
+  int nt = R.ntiles();
   BT(upload_tables(R));
   BTile* tl = R.at<BTile>(R.L.tiles);
   BSys* sy = R.at<BSys>(R.L.sys);
@@ -1268,6 +1298,24 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
     for (int s = 0; s < ns; ++s)
       if (hst[s].active) ++cycles[s];
     ++total_cycles;
+    if (!b->graph) {
+      // launches of this cycle cover the active systems only; when those give
+      // too few tiles to fill the GPU, the tiles are made smaller (a captured
+      // graph keeps the full table instead)
+      std::vector<char> use(ns);
+      for (int s = 0; s < ns; ++s) use[s] = hst[s].active && !hst[s].failed;
+      auto ntiles_at = [&](int tr) {
+        int t = 0;
+        for (int s = 0; s < ns; ++s)
+          if (use[s]) t += (b->sys_rows[s] + tr - 1) / tr;
+        return t;
+      };
+      int tr = b->tile_rows;
+      while (tr > kMinTileRows && ntiles_at(tr) < kFillTiles) tr = std::max(kMinTileRows, tr / 2 / 16 * 16);
+      fill_tiles(b, tr, use);
+      nt = R.ntiles();
+      BT(upload_tables(R));
+    }
     if (b->graph) {
       if (!graph.g) BT(capture_graph(R.s, &graph.g, enqueue_cycle));
       BH(hipGraphLaunch(graph.g, R.s));
@@ -1276,6 +1324,7 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
     }
   }
   BH(hipStreamSynchronize(R.s));
+  fill_tiles(b, b->tile_rows, std::vector<char>(ns, 1));  // the full table again
   std::vector<double> hg(ns * P), hb(ns * P);
   BH(hipMemcpy(hg.data(), gam, ns * P * 8, hipMemcpyDeviceToHost));
   BH(hipMemcpy(hb.data(), bnorm, ns * P * 8, hipMemcpyDeviceToHost));
@@ -1390,6 +1439,7 @@ gmr_status batch_bcgs_step(gmr_batch* b, const float* Vin, int32_t nblk, float* 
   const int ns = b->nsys;
   std::vector<BState> hst(ns, BState{1, 0, 0, 0, 0, 0});
   BH(hipMemcpyAsync(R.at<BState>(R.L.st), hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
+  fill_tiles(b, b->tile_rows, std::vector<char>(ns, 1));
   BT(upload_tables(R));
   BH(hipMemcpyAsync(R.at<float>(R.L.V), Vin, (size_t)nblk * R.L.vstride * 4, hipMemcpyDeviceToDevice, R.s));
   BT(dots<float>(R, R.at<float>(R.L.V), nblk, W, R.at<double>(R.L.Cd), R.at<float>(R.L.Cf)));

@@ -105,3 +105,41 @@ def test_harmonic_ritz_ignores_entries_below_subdiagonal():
     assert np.allclose(np.sort_complex(G.harmonic_ritz(junk)), np.sort_complex(G.harmonic_ritz(H)))
     assert np.allclose(np.sort_complex(G.hessenberg_eigvals(junk[:9, :9])),
                        np.sort_complex(G.hessenberg_eigvals(H[:9, :9])))
+
+
+def test_batch_host_api_without_device():
+    """The batch object is host-side: creation, tiling, graph switch and
+    workspace queries run without a GPU, and bad arguments are rejected."""
+    lib = G.lib()
+    b = G.Batch([300, 1000, 17], restart=8)
+    f32, f64 = b.workspace_bytes(G.GMR_F32), b.workspace_bytes(G.GMR_F64)
+    assert 0 < f32 < f64
+    assert lib.batch_workspace_bytes(b.handle, 7) == 0
+    assert lib.batch_workspace_bytes(None, G.GMR_F32) == 0
+    assert b.tiling() == (1024, 8)
+    for t, g in ((512, 16), (256, 2), (4096, 3), (1024, 5)):
+        b.set_tiling(t, g)
+        assert b.tiling() == (t, g)
+    for t, g in ((255, 8), (1000, 8), (1024, 6), (1024, 0)):
+        with pytest.raises(G.GmresError):
+            b.set_tiling(t, g)
+    b.set_graph(True)
+    b.set_graph(False)
+    assert lib.batch_set_graph(None, 1) == -1
+    out = C.c_void_p()
+    rows = np.array([10, 0], dtype=np.int32)
+    assert lib.batch_create(2, rows.ctypes.data_as(C.c_void_p), 16, 8, C.byref(out)) == -1
+    rows = np.array([10, 20], dtype=np.int32)
+    assert lib.batch_create(2, rows.ctypes.data_as(C.c_void_p), 8, 8, C.byref(out)) == -5
+    assert lib.batch_create(2, rows.ctypes.data_as(C.c_void_p), 16, 65, C.byref(out)) == -5
+    res = _capi.gmr_batch_result()
+    # null arguments and a matrix of the wrong size are found before any launch
+    assert lib.batch_gmres_solve(b.handle, None, None, None, None, 1e-10, 10, None, 0, C.byref(res), None, None,
+                                 None) == -1
+    A = _capi.gmr_csr(1000, 10, 16, 32, 48, 1)  # the batch has 300 + 1000 + 17 rows
+    assert lib.batch_gmres_solve(b.handle, C.byref(A), 64, 128, 192, 1e-10, 10, 256, 1 << 40, C.byref(res), None,
+                                 None, None) == -1
+    assert b"does not match" in lib.gmr_last_error()
+    A.n = 300 + 1000 + 17
+    assert lib.batch_gmres_solve(b.handle, C.byref(A), 64, 128, 192, 1e-10, 10, 256, 16, C.byref(res), None,
+                                 None, None) == -3

@@ -140,16 +140,28 @@ def test_graph_replay_matches_eager(inner):
     ref = b.solve(A64, Ain, Bd, X0, Zd, ws, tol=1e-10, max_cycles=300)
     assert ref["status"] == 0
     Xref = host(X0)
+    # eager launches are repeatable bit for bit
+    X2 = torch.zeros_like(Bd)
+    b.solve(A64, Ain, Bd, X2, Zd, ws, tol=1e-10, max_cycles=300)
+    assert np.array_equal(host(X2), Xref)
+    # the graph keeps the full tile table every cycle, while eager launches cover
+    # only the active systems (other partial sums): the same solution to the
+    # tolerance, and the replays are bitwise equal to each other
     b.set_graph(True)
+    Xg = None
     for rep in range(3):  # replays of a freshly captured graph, with eager work in between
         torch.cuda.synchronize()
         _ = (Bd * 2.0).sum().item()
         X1 = torch.zeros_like(Bd)
         out = b.solve(A64, Ain, Bd, X1, Zd, ws, tol=1e-10, max_cycles=300)
         say("graph", inner, rep, out["status_name"], out["cycles"], out["block_iters"])
-        assert out["status"] == 0 and out["cycles"] == ref["cycles"]
-        assert out["block_iters"] == ref["block_iters"]
-        assert np.array_equal(host(X1), Xref)
+        assert out["status"] == 0 and out["max_rel_res"] <= 1e-10
+        assert abs(out["cycles"] - ref["cycles"]) <= 1
+        Xh = host(X1)
+        assert np.linalg.norm(Xh - Xref) / np.linalg.norm(Xref) <= 1e-7
+        if Xg is None:
+            Xg = Xh
+        assert np.array_equal(Xh, Xg)
     b.set_graph(False)
 
 
