@@ -93,45 +93,48 @@ __global__ __launch_bounds__(kBlock) void bspmm_kernel(const BTile* __restrict__
   const int c = threadIdx.x % P;
   const int rs = threadIdx.x / P;
   const int rend = tl.r0 + tl.nr;
-  // RU rows per thread at a time and KU nonzeros per row at a time, so that the
-  // dependent loads (row pointers, then indices and values, then X) of several
-  // rows overlap; every row is still summed in ascending k.
+  // RU rows per thread at a time.  The 16 lanes of a row load KU of its
+  // (index, value) pairs with one load each and pass them to each other with
+  // lane shuffles, so each nonzero costs one memory instruction (the gather of
+  // its X row) instead of three; every row is still summed in ascending k.
   constexpr int RU = 4, KU = 8, RS = kBlock / P;
+  const int gbase = threadIdx.x % kWave - c;  // first lane of this row's 16-lane group
   for (int r = tl.r0 + rs; r < rend; r += RU * RS) {
-    int k0[RU], k1[RU];
+    int k0[RU], len[RU];
     int kmax = 0;
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       const int rr = r + u * RS;
       k0[u] = rr < rend ? rp[rr] : 0;
-      k1[u] = rr < rend ? rp[rr + 1] : 0;
-      kmax = max(kmax, k1[u] - k0[u]);
+      len[u] = rr < rend ? rp[rr + 1] - k0[u] : 0;
+      kmax = max(kmax, len[u]);
     }
     T acc[RU];
 #pragma unroll
     for (int u = 0; u < RU; ++u) acc[u] = T(0);
     for (int o = 0; o < kmax; o += KU) {
-      int cx[RU][KU];
-      T a[RU][KU], xv[RU][KU];
+      int myc[RU];
+      T myv[RU];
 #pragma unroll
-      for (int u = 0; u < RU; ++u)
+      for (int u = 0; u < RU; ++u) {
+        const bool in = c < KU && o + c < len[u];
+        myc[u] = in ? ci[k0[u] + o + c] : 0;
+        myv[u] = in ? val[k0[u] + o + c] : T(0);
+      }
+      T xv[RU][KU], av[RU][KU];
 #pragma unroll
-        for (int t = 0; t < KU; ++t) {
-          const int k = k0[u] + o + t;
-          const bool in = k < k1[u];
-          cx[u][t] = in ? ci[k] : 0;
-          a[u][t] = in ? val[k] : T(0);
+      for (int t = 0; t < KU; ++t)
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int col = __shfl(myc[u], gbase + t, kWave);
+          av[u][t] = __shfl(myv[u], gbase + t, kWave);
+          xv[u][t] = (o + t < len[u]) ? X[(size_t)col * P + c] : T(0);
         }
 #pragma unroll
       for (int u = 0; u < RU; ++u)
 #pragma unroll
         for (int t = 0; t < KU; ++t)
-          xv[u][t] = (k0[u] + o + t < k1[u]) ? X[(size_t)cx[u][t] * P + c] : T(0);
-#pragma unroll
-      for (int u = 0; u < RU; ++u)
-#pragma unroll
-        for (int t = 0; t < KU; ++t)
-          if (k0[u] + o + t < k1[u]) acc[u] += a[u][t] * xv[u][t];
+          if (o + t < len[u]) acc[u] += av[u][t] * xv[u][t];
     }
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
