@@ -233,9 +233,10 @@ size_t batch_workspace_bytes(const gmr_batch* b, int32_t inner_dtype);
 
 /* Tiling of the matrix-core kernels: rows per tile (multiple of 16, >= 256) and
  * the block-dots variant: 4, 8 or 16 basis blocks accumulated per pass with a
- * cross-wave reduction in LDS, or the wave-split variants 2, 3, 5 (each wave
+ * cross-wave reduction in LDS; the wave-split variants 2, 3, 5 (each wave
  * accumulates 2, 4, 4 blocks over all rows with 8, 4, 8 four-row slices in
- * flight).  Float64 uses 8 where 16 is set. */
+ * flight); or 6, 7: 8 or 16 blocks per pass read with 16-byte loads staged
+ * through LDS.  Float64 uses 8 blocks where 16 is set. */
 gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_blocks);
 gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* group_blocks);
 
@@ -248,7 +249,7 @@ gmr_status batch_set_graph(gmr_batch* b, int32_t on);
 
 /* Times the block Gram-Schmidt contraction pair (dots and update over m/2
  * blocks, every system active) for every candidate tiling (tile rows 512,
- * 1024, 2048, 4096 x dots variants 4, 8, 16, 2, 3, 5) on the batch's own workspace (its
+ * 1024, 2048, 4096 x dots variants 4, 8, 16, 2, 3, 5, 6, 7) on the batch's own workspace (its
  * contents are overwritten), keeps the fastest and reports it: *best_ms is
  * the fastest of five timed repetitions (best_* may be NULL).  Synchronous. */
 gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,

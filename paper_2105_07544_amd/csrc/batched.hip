@@ -345,6 +345,75 @@ __global__ __launch_bounds__(kBlock) void bdots_w_kernel(const BTile* __restrict
   }
 }
 
+// The LDS-reduced products with wide loads: each wave stages its 16-row slab
+// of every block (16 rows x 16 columns: one 16-byte (float) or 32-byte
+// (double) vector per lane, lane l holding row l/4, columns 4(l%4)..+3)
+// through LDS and reads it back in the operand layout.  The wave reads each
+// slab with one vector load per block instead of four scalar ones.  The
+// staging area is reused for the cross-wave reduction at the end of a group.
+template <class T, int GB>
+__global__ __launch_bounds__(kBlock) void bdots_v_kernel(const BTile* __restrict__ tiles,
+                                                         const BState* __restrict__ st,
+                                                         const T* __restrict__ V, size_t vstride,
+                                                         int nblk, const T* __restrict__ W,
+                                                         T* __restrict__ partial, size_t pstride) {
+  typedef typename Mx<T>::v4 v4;
+  __shared__ __align__(16) T s_st[kWavesPerBlock][GB][PP];
+  const BTile tl = tiles[blockIdx.x];
+  if (!running(st[tl.sys])) return;
+  const int lane = threadIdx.x % kWave;
+  const int wave = threadIdx.x / kWave;
+  const int rsub = lane / P;
+  const int col = lane % P;
+  const int lr = lane / 4;       // staged row of this lane
+  const int lc = (lane % 4) * 4; // first staged column
+  const int rend = tl.r0 + tl.nr;
+  const v4 z = v4{T(0), T(0), T(0), T(0)};
+  for (int g0 = 0; g0 < nblk; g0 += GB) {
+    typename Mx<T>::v4 acc[GB];
+#pragma unroll
+    for (int b = 0; b < GB; ++b) acc[b] = z;
+    for (int slab = tl.r0 + 16 * wave; slab < rend; slab += 16 * kWavesPerBlock) {
+      const int row = slab + lr;
+      const bool ok = row < rend;
+      v4 vv[GB];
+#pragma unroll
+      for (int b = 0; b < GB; ++b)
+        vv[b] = (ok && g0 + b < nblk) ? *reinterpret_cast<const v4*>(V + (size_t)(g0 + b) * vstride + (size_t)row * P + lc)
+                                      : z;
+      T bw[4];
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        const int wr = slab + 4 * sl + rsub;
+        bw[sl] = wr < rend ? W[(size_t)wr * P + col] : T(0);
+      }
+#pragma unroll
+      for (int b = 0; b < GB; ++b) *reinterpret_cast<v4*>(&s_st[wave][b][lr * P + lc]) = vv[b];
+#pragma unroll
+      for (int b = 0; b < GB; ++b)
+        if (g0 + b < nblk) {
+#pragma unroll
+          for (int sl = 0; sl < 4; ++sl)
+            acc[b] = Mx<T>::mfma(s_st[wave][b][(4 * sl + rsub) * P + col], bw[sl], acc[b]);
+        }
+    }
+    __syncthreads();  // every wave is done staging: the area holds the partial results now
+#pragma unroll
+    for (int b = 0; b < GB; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s_st[wave][b][Mx<T>::row(rsub, q) * P + col] = acc[b][q];
+    __syncthreads();
+    for (int b = 0; b < GB && g0 + b < nblk; ++b) {
+      const int e = threadIdx.x;
+      T sum = s_st[0][b][e];
+#pragma unroll
+      for (int w = 1; w < kWavesPerBlock; ++w) sum += s_st[w][b][e];
+      partial[(size_t)blockIdx.x * pstride + (size_t)(g0 + b) * PP + e] = sum;
+    }
+    __syncthreads();
+  }
+}
+
 // Per system and block b: the tile partials added in tile order (float64),
 // stored as Cd[s][b][.] and rounded into Cf[s][b][.] (matrix-core operand).
 template <class T>
@@ -887,8 +956,11 @@ constexpr int kMinTileRows = 256;
 constexpr int kFillTiles = 1024;
 // group_blocks codes of the wave-split dots kernel (blocks per wave x row slices)
 constexpr int kDotsW2x8 = 2, kDotsW4x4 = 3, kDotsW4x8 = 5;
+// group_blocks codes of the staged wide-load dots kernel (8 or 16 blocks per pass)
+constexpr int kDotsV8 = 6, kDotsV16 = 7;
 inline bool valid_gb(int g) {
-  return g == 4 || g == 8 || g == 16 || g == kDotsW2x8 || g == kDotsW4x4 || g == kDotsW4x8;
+  return g == 4 || g == 8 || g == 16 || g == kDotsW2x8 || g == kDotsW4x4 || g == kDotsW4x8 || g == kDotsV8 ||
+         g == kDotsV16;
 }
 inline size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -1002,6 +1074,11 @@ gmr_status dots(const BRun& R, const T* V, int nblk, const T* W, double* Cd, T* 
     case kDotsW2x8: bdots_w_kernel<T, 2, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
     case kDotsW4x4: bdots_w_kernel<T, 4, 4><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
     case kDotsW4x8: bdots_w_kernel<T, 4, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    case kDotsV8: bdots_v_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    case kDotsV16:
+      if constexpr (sizeof(T) == 4) bdots_v_kernel<T, 16><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps);
+      else bdots_v_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps);
+      break;
     default: bdots_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
   }
   BT(launch_check("bdots_kernel"));
@@ -1136,8 +1213,8 @@ gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_block
   if (tile_rows < kMinTileRows || tile_rows % 16 != 0)
     return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: tile_rows must be a multiple of 16, >= 256");
   if (!valid_gb(group_blocks))
-    return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: group_blocks must be 4, 8, 16 (LDS-reduced dots) "
-                                      "or 2, 3, 5 (wave-split dots)");
+    return gmr::fail(GMR_ERR_INVALID, "batch_set_tiling: group_blocks must be 4, 8, 16 (LDS-reduced dots), "
+                                      "2, 3, 5 (wave-split dots) or 6, 7 (staged wide-load dots)");
   build_tiles(b, tile_rows);
   b->gb = group_blocks;
   return GMR_OK;
@@ -1386,7 +1463,7 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
   BH(hipEventCreate(&e1));
   const int nb = std::max(1, b->m / 2);
   const int cand_rows[] = {512, 1024, 2048, 4096};
-  const int cand_gb[] = {4, 8, 16, kDotsW2x8, kDotsW4x4, kDotsW4x8};
+  const int cand_gb[] = {4, 8, 16, kDotsW2x8, kDotsW4x4, kDotsW4x8, kDotsV8, kDotsV16};
   double best = 1e30;
   int bt = b->tile_rows, bg = b->gb;
   gmr_status status = GMR_OK;

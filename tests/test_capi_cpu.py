@@ -120,7 +120,7 @@ def test_batch_host_api_without_device():
     for t, g in ((512, 16), (256, 2), (4096, 3), (1024, 5)):
         b.set_tiling(t, g)
         assert b.tiling() == (t, g)
-    for t, g in ((255, 8), (1000, 8), (1024, 6), (1024, 0)):
+    for t, g in ((255, 8), (1000, 8), (1024, 9), (1024, 0)):
         with pytest.raises(G.GmresError):
             b.set_tiling(t, g)
     b.set_graph(True)
