@@ -395,6 +395,72 @@ __device__ __forceinline__ void cgs_dots_body(int n, int j, const T* __restrict_
   publish_col_partials<K, T, NQ>(acc, j, partial);
 }
 
+// Pass 1 with four rows per lane: lane l of row group grp owns rows
+// 256 grp + 4 l .. + 3 and reads them with one 16-byte (float) or 32-byte
+// (double) vector load per column (V columns and w are 256-byte aligned); the
+// four products of a column are added in the lane before the butterfly.
+template <class T, int K, int NQ>
+__device__ __forceinline__ void cgs_dots4_body(int n, int j, const T* __restrict__ V, int64_t ldv,
+                                               const T* __restrict__ w, double* partial,
+                                               const int* __restrict__ done) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  constexpr int KO = Butterfly<K>::KOut;
+  if (done && *done) return;
+  const int lane = threadIdx.x % kWave;
+  const int gw = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const int G = gridDim.x * kWavesPerBlock;
+  const int ngrp = (n + 4 * kWave - 1) / (4 * kWave);
+  T acc[NQ][KO];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int i = 0; i < KO; ++i) acc[q][i] = T(0);
+  for (int grp = gw; grp < ngrp; grp += G) {
+    const int r = grp * 4 * kWave + 4 * lane;
+    const bool full = r + 3 < n;
+    v4 wv;
+    if (full) {
+      wv = *reinterpret_cast<const v4*>(w + r);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) wv[e] = r + e < n ? w[r + e] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q * K < j) {
+        T a[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          const int col = q * K + c;
+          v4 v = v4{T(0), T(0), T(0), T(0)};
+          if (col < j) {
+            const T* Vc = V + (size_t)col * ldv + r;
+            if (full) {
+              v = *reinterpret_cast<const v4*>(Vc);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) v[e] = r + e < n ? Vc[e] : T(0);
+            }
+          }
+          a[c] = ((v.x * wv.x + v.y * wv.y) + v.z * wv.z) + v.w * wv.w;
+        }
+        Butterfly<K>::run(a, lane);
+#pragma unroll
+        for (int i = 0; i < KO; ++i) acc[q][i] += a[i];
+      }
+    }
+  }
+  publish_col_partials<K, T, NQ>(acc, j, partial);
+}
+
+template <class T, int K, int NQ>
+__global__ __launch_bounds__(kBlock) void cgs_dots4_kernel(int n, int j, const T* __restrict__ V,
+                                                           int64_t ldv, const T* __restrict__ w,
+                                                           double* partial,
+                                                           const int* __restrict__ done) {
+  cgs_dots4_body<T, K, NQ>(n, j, V, ldv, w, partial, done);
+}
+
 template <class T, int K, int NQ>
 __global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T* __restrict__ V,
                                                           int64_t ldv, const T* __restrict__ w,
@@ -473,6 +539,14 @@ __device__ __forceinline__ void update_rows4(int j, const T* __restrict__ V, int
   out[3] = wv.w;
 }
 
+// Whether the four-row vector form applies: V's columns and w aligned to the
+// 4-element vector (the solver's own buffers always are; a caller's may not).
+template <class T>
+__device__ __forceinline__ bool rows4_ok(const T* V, int64_t ldv, const T* w) {
+  return ((reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(w)) & (4 * sizeof(T) - 1)) == 0 &&
+         (ldv & 3) == 0;
+}
+
 // The same for one row (the rows past the last multiple of 4).
 template <class T>
 __device__ __forceinline__ T update_row(int j, const T* __restrict__ V, int64_t ldv,
@@ -495,7 +569,7 @@ __device__ __forceinline__ void cgs_update_body(int n, int j, const T* __restric
   if (done && *done) return;
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
   __syncthreads();
-  const int nq = n / 4;
+  const int nq = rows4_ok(V, ldv, w) ? n / 4 : 0;
   T o[4];
   for (int q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock)
     update_rows4<T>(j, V, ldv, s_h, w, 4 * q, o);
@@ -619,7 +693,7 @@ __device__ __forceinline__ void cgs_update_norm_body(
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
   __syncthreads();
   T sq = T(0);
-  const int nq = n / 4;
+  const int nq = rows4_ok(V, ldv, w) ? n / 4 : 0;
   T o[4];
   for (int q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
     update_rows4<T>(j, V, ldv, s_h, w, 4 * q, o);

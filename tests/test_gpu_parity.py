@@ -113,13 +113,16 @@ def _basis(n, k, seed, dt):
 
 @pytest.mark.parametrize("k", [1, 5, 8, 9, 17, 33, 50, 64, 65, 100, 129, 200, 256])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_cgs2_orth_matches_oracle(k, prec):
+@pytest.mark.parametrize("aligned", [False, True])
+def test_cgs2_orth_matches_oracle(k, prec, aligned):
+    # aligned: every column starts on a 256-byte boundary (the four-row vector
+    # passes); otherwise ldv is not a multiple of 4 (the one-row passes)
     n = 3001 + 17 * k
-    say("cgs2", k, prec, n)
+    say("cgs2", k, prec, n, aligned)
     dt = np.float64 if prec == "f64" else np.float32
     V = _basis(n, k, k, dt)
     w = np.random.default_rng(100 + k).standard_normal(n).astype(dt)
-    ldv = n + 64
+    ldv = (n + 63) // 64 * 64 if aligned else n + 64 + (1 if n % 2 == 0 else 0)
     Vd = torch.zeros((k, ldv), dtype=torch.float64 if prec == "f64" else torch.float32, device=DEV)
     Vd[:, :n] = torch.from_numpy(np.ascontiguousarray(V.T)).to(DEV)
     wd = torch.from_numpy(w.copy()).to(DEV)
