@@ -236,7 +236,8 @@ size_t batch_workspace_bytes(const gmr_batch* b, int32_t inner_dtype);
  * cross-wave reduction in LDS; the wave-split variants 2, 3, 5 (each wave
  * accumulates 2, 4, 4 blocks over all rows with 8, 4, 8 four-row slices in
  * flight); or 6, 7: 8 or 16 blocks per pass read with 16-byte loads staged
- * through LDS.  Float64 uses 8 blocks where 16 is set. */
+ * through LDS.  Float64 uses 8 blocks where 16 is set, and the scalar-load
+ * 8-block form for 6 and 7. */
 gmr_status batch_set_tiling(gmr_batch* b, int32_t tile_rows, int32_t group_blocks);
 gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* group_blocks);
 
@@ -247,8 +248,8 @@ gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* gro
  * Results are identical to the eager launches. */
 gmr_status batch_set_graph(gmr_batch* b, int32_t on);
 
-/* Times the block Gram-Schmidt contraction pair (dots and update over m/2
- * blocks, every system active) for every candidate tiling (tile rows 512,
+/* Times the block Gram-Schmidt contraction pair (dots and update at about
+ * (m+1)/8, (m+1)/2 and 7(m+1)/8 blocks, every system active) for every candidate tiling (tile rows 512,
  * 1024, 2048, 4096 x dots variants 4, 8, 16, 2, 3, 5, 6, 7) on the batch's own workspace (its
  * contents are overwritten), keeps the fastest and reports it: *best_ms is
  * the fastest of five timed repetitions (best_* may be NULL).  Synchronous. */

@@ -379,8 +379,9 @@ __global__ __launch_bounds__(kBlock) void bdots_v_kernel(const BTile* __restrict
       v4 vv[GB];
 #pragma unroll
       for (int b = 0; b < GB; ++b)
-        vv[b] = (ok && g0 + b < nblk) ? *reinterpret_cast<const v4*>(V + (size_t)(g0 + b) * vstride + (size_t)row * P + lc)
-                                      : z;
+        vv[b] = (ok && g0 + b < nblk)
+                    ? __builtin_nontemporal_load(reinterpret_cast<const v4*>(V + (size_t)(g0 + b) * vstride + (size_t)row * P + lc))
+                    : z;
       T bw[4];
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
@@ -448,6 +449,16 @@ __global__ __launch_bounds__(kBlock) void bfinish_c_kernel(const BSys* __restric
 // ---------------------------------------------------------------------------
 enum { kSub = 0, kSet = 1, kXupd = 2 };
 
+// Basis loads of the block update.  The basis is streamed once per pass and
+// is far larger than the caches, so float32 loads are non-temporal (keeps W
+// and the coefficients cached: config-4 float32 solve 22.5 s -> 21.0 s);
+// float64 measured no better with them.
+template <class T, class V4>
+__device__ __forceinline__ V4 ld_basis(const V4* p) {
+  if constexpr (sizeof(T) == 4) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 template <class T, int MODE>
 __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__ tiles,
                                                        const BState* __restrict__ st,
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
       v4 a[8], cb[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        a[u] = aok ? *(const v4*)(Vr + (size_t)(b + u) * vstride) : z;
+        a[u] = aok ? ld_basis<T>((const v4*)(Vr + (size_t)(b + u) * vstride)) : z;
         cb[u] = *(const v4*)(Cl + (b + u) * PP);
       }
 #pragma unroll
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
         }
     }
     for (; b < nblk; ++b) {
-      const v4 a0 = aok ? *(const v4*)(Vr + (size_t)b * vstride) : z;
+      const v4 a0 = aok ? ld_basis<T>((const v4*)(Vr + (size_t)b * vstride)) : z;
       const v4 c0 = *(const v4*)(Cl + b * PP);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) acc = Mx<T>::mfma(a0[kk], c0[kk], acc);
@@ -1074,10 +1085,16 @@ gmr_status dots(const BRun& R, const T* V, int nblk, const T* W, double* Cd, T* 
     case kDotsW2x8: bdots_w_kernel<T, 2, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
     case kDotsW4x4: bdots_w_kernel<T, 4, 4><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
     case kDotsW4x8: bdots_w_kernel<T, 4, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
-    case kDotsV8: bdots_v_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
+    case kDotsV8:
     case kDotsV16:
-      if constexpr (sizeof(T) == 4) bdots_v_kernel<T, 16><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps);
-      else bdots_v_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps);
+      // float64 keeps the scalar-load variant: its 32-byte staged form was slower
+      // (float64 config-4 solve 40.4 s -> 42.4 s)
+      if constexpr (sizeof(T) == 8)
+        bdots_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps);
+      else if (gb == kDotsV8)
+        bdots_v_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps);
+      else
+        bdots_v_kernel<T, 16><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps);
       break;
     default: bdots_kernel<T, 8><<<g, kBlock, 0, R.s>>>(tl, st, V, vs, nblk, W, part, ps); break;
   }
@@ -1444,9 +1461,10 @@ gmr_status batch_gmres_solve(gmr_batch* b, const gmr_csr* A64, const double* B, 
                             sys_cycles, sys_rel_res, stream);
 }
 
-// Times the block Gram-Schmidt contraction pair (dots + update over nblk = m/2
-// blocks) for every candidate tiling on the batch's own buffers and keeps the
-// fastest.  The workspace is the solve's; its contents are overwritten.
+// Times the block Gram-Schmidt contraction pair (dots + update) at three basis
+// sizes, about (m+1)/8, (m+1)/2 and 7(m+1)/8 blocks, for every candidate
+// tiling on the batch's own buffers and keeps the fastest.  The workspace is
+// the solve's; its contents are overwritten.
 gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,
                           int32_t* best_group_blocks, double* best_ms, void* stream) {
   if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_autotune: null batch");
@@ -1461,7 +1479,9 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
   hipEvent_t e0, e1;
   BH(hipEventCreate(&e0));
   BH(hipEventCreate(&e1));
-  const int nb = std::max(1, b->m / 2);
+  // a block step of a cycle sees every basis size from 1 to m + 1: time the
+  // pair at a small, a middle and a large one
+  const int nbs[3] = {std::max(1, (b->m + 1) / 8), std::max(1, (b->m + 1) / 2), std::max(1, (b->m + 1) * 7 / 8)};
   const int cand_rows[] = {512, 1024, 2048, 4096};
   const int cand_gb[] = {4, 8, 16, kDotsW2x8, kDotsW4x4, kDotsW4x8, kDotsV8, kDotsV16};
   double best = 1e30;
@@ -1477,12 +1497,15 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
       float ms = 1e30f;
       for (int rep = 0; rep < 6; ++rep) {
         if (hipEventRecord(e0, R.s) != hipSuccess) { status = GMR_ERR_HIP; break; }
-        if ((status = dots<float>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd),
-                                  R.at<float>(R.L.Cf))) != GMR_OK)
-          break;
-        if ((status = gemm<float, kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))) !=
-            GMR_OK)
-          break;
+        for (int nb : nbs) {
+          if ((status = dots<float>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd),
+                                    R.at<float>(R.L.Cf))) != GMR_OK)
+            break;
+          if ((status = gemm<float, kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))) !=
+              GMR_OK)
+            break;
+        }
+        if (status != GMR_OK) break;
         if (hipEventRecord(e1, R.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { status = GMR_ERR_HIP; break; }
         float t = 0.f;
         (void)hipEventElapsedTime(&t, e0, e1);
