@@ -495,48 +495,78 @@ __global__ __launch_bounds__(kBlock) void bgemm_kernel(const BTile* __restrict__
     gc = gam[tl.sys * P + c];
     upd_col = !(gc <= tol * bnorm[tl.sys * P + c]);
   }
-  for (int r0 = tl.r0 + 16 * wave; r0 < rend; r0 += 16 * kWavesPerBlock) {
-    const int arow = r0 + lane % 16;
-    const bool aok = arow < rend;
-    const v4 z = v4{T(0), T(0), T(0), T(0)};
-    v4 acc = z;
-    const int g = lane / 16;
-    // two accumulators (even and odd b) so that consecutive MFMAs are independent
-    v4 acc1 = z;
-    const T* Vr = V + (size_t)arow * P + 4 * g;
-    const T* Cl = s_C + (g * P + lane % 16) * 4;
-    // eight blocks per iteration: eight vector loads in flight per lane
+  // RG 16-row groups per iteration (rows r0 .. r0+15, r0+64 .. r0+79, ... of the
+  // wave's stride) would share the coefficient reads; two measured slower than
+  // one (float32 config 4: 21.1 s -> 21.5 s, from the lower occupancy).  The old
+  // output values are loaded before the first MFMA.
+  const int g = lane / 16;
+  const T* Cl = s_C + (g * P + lane % 16) * 4;
+  const v4 z = v4{T(0), T(0), T(0), T(0)};
+  constexpr int RG = 1;
+  for (int r0 = tl.r0 + 16 * wave; r0 < rend; r0 += 16 * kWavesPerBlock * RG) {
+    const T* Vr[RG];
+    bool aok[RG];
+    T old[RG][4];
+#pragma unroll
+    for (int h = 0; h < RG; ++h) {
+      const int rg = r0 + 16 * kWavesPerBlock * h;
+      const int arow = rg + lane % 16;
+      aok[h] = arow < rend;
+      Vr[h] = V + (size_t)arow * P + 4 * g;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = rg + Mx<T>::row(g, q);
+        old[h][q] = T(0);
+        if constexpr (MODE == kSub) {
+          if (row < rend) old[h][q] = out[(size_t)row * P + lane % 16];
+        }
+      }
+    }
+    // two accumulators per group (even and odd b) so that consecutive MFMAs are independent
+    v4 acc[RG][2];
+#pragma unroll
+    for (int h = 0; h < RG; ++h) acc[h][0] = acc[h][1] = z;
     int b = 0;
     for (; b + 7 < nblk; b += 8) {
-      v4 a[8], cb[8];
+      v4 a[RG][8], cb[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        a[u] = aok ? ld_basis<T>((const v4*)(Vr + (size_t)(b + u) * vstride)) : z;
         cb[u] = *(const v4*)(Cl + (b + u) * PP);
+#pragma unroll
+        for (int h = 0; h < RG; ++h) a[h][u] = aok[h] ? ld_basis<T>((const v4*)(Vr[h] + (size_t)(b + u) * vstride)) : z;
       }
 #pragma unroll
       for (int u = 0; u < 8; u += 2)
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          acc = Mx<T>::mfma(a[u][kk], cb[u][kk], acc);
-          acc1 = Mx<T>::mfma(a[u + 1][kk], cb[u + 1][kk], acc1);
-        }
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int h = 0; h < RG; ++h) {
+            acc[h][0] = Mx<T>::mfma(a[h][u][kk], cb[u][kk], acc[h][0]);
+            acc[h][1] = Mx<T>::mfma(a[h][u + 1][kk], cb[u + 1][kk], acc[h][1]);
+          }
     }
     for (; b < nblk; ++b) {
-      const v4 a0 = aok ? ld_basis<T>((const v4*)(Vr + (size_t)b * vstride)) : z;
       const v4 c0 = *(const v4*)(Cl + b * PP);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc = Mx<T>::mfma(a0[kk], c0[kk], acc);
-    }
-    acc += acc1;
+      for (int h = 0; h < RG; ++h) {
+        const v4 a0 = aok[h] ? ld_basis<T>((const v4*)(Vr[h] + (size_t)b * vstride)) : z;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = r0 + Mx<T>::row(lane / 16, q);
-      if (row < rend) {
-        const size_t idx = (size_t)row * P + lane % 16;
-        if constexpr (MODE == kSub) out[idx] -= acc[q];
-        else if constexpr (MODE == kSet) out[idx] = acc[q];
-        else if (upd_col) X64[idx] += gc * double(acc[q]);
+        for (int kk = 0; kk < 4; ++kk) acc[h][0] = Mx<T>::mfma(a0[kk], c0[kk], acc[h][0]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < RG; ++h) {
+      const v4 d = acc[h][0] + acc[h][1];
+      const int rg = r0 + 16 * kWavesPerBlock * h;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = rg + Mx<T>::row(g, q);
+        if (row < rend) {
+          const size_t idx = (size_t)row * P + lane % 16;
+          if constexpr (MODE == kSub) out[idx] = old[h][q] - d[q];
+          else if constexpr (MODE == kSet) out[idx] = d[q];
+          else if (upd_col) X64[idx] += gc * double(d[q]);
+        }
       }
     }
   }
