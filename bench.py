@@ -16,6 +16,8 @@ Other workloads (each prints its own line; the default line is the one above):
              block GMRES(50)-IR on the matrix cores
   predictor  the learned parameter predictor: label, train on the GPU, and
              compare held-out time to solution with the fixed (m=50, d=0, f32)
+  fd         GMRES-FD switch-point sweep on the 3D Laplacian 200^3 (b = ones):
+             float32 GMRES(50) for s iterations, then float64 GMRES(50)
 
 Extra fields: the float64 GMRES time on the same GPU and the ratio,
 per-kernel-family time and GB/s (the analogue of the paper's Table I), the
@@ -297,6 +299,95 @@ def single_system(args, kind):
     return out
 
 
+def fd_sweep(args):
+    """GMRES-FD switch-point sweep (§V-A): float32 GMRES(m) for s iterations, then
+    float64 GMRES(m) from its iterate, for s = 0, stride, 2*stride, ...; beside it
+    one GMRES-IR solve and one float64 GMRES(m) solve of the same system."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07544_amd as G
+    import workloads as W
+
+    dev = "cuda:0"
+    N = args.grid or 200
+    log("bench: building the workload")
+    prob = W.fd_laplace3d(N, restart=args.restart or 50)
+    m = prob.restart
+    desc = (f"GMRES-FD switch-point sweep vs GMRES({m})-IR vs float64 GMRES({m}): 3D Laplacian 6/-1 "
+            f"on {N}^3 (n={prob.A.n}, nnz={prob.A.nnz}), b=ones, x0=0, tol 1e-10")
+    A64 = G.DeviceCSR.from_host(prob.A, dev)
+    A32 = A64.to_f32()
+    b = torch.from_numpy(prob.b).to(dev)
+    x = torch.zeros_like(b)
+    ws = G.alloc_workspace(G.fd_workspace_bytes(prob.A.n, m), dev)
+    Ah = host_csr(prob.A)
+
+    def host_rel():
+        xh = x.cpu().numpy()
+        return float(np.linalg.norm(prob.b - Ah @ xh) / np.linalg.norm(prob.b))
+
+    def ir(prof="none"):
+        x.zero_()
+        return G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws, prof=prof)[1]
+
+    log("bench: warmup")
+    for _ in range(args.warmup):
+        ir()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    log(f"bench: timing {steps} GMRES-IR solves")
+    t0 = time.perf_counter()
+    rir = [ir() for _ in range(steps)]
+    t_ir = (time.perf_counter() - t0) / steps
+    assert all(r.converged for r in rir), [r.status_name for r in rir]
+    rel_ir = host_rel()
+    log(f"bench: IR {t_ir:.3f} s, {rir[-1].iters} iters")
+    pr = ir(prof="cgs_update_dots")
+    achieved = pr.prof_bytes / (pr.prof_ms * 1e-3) / 1e9 if pr.prof_ms > 0 else 0.0
+    x.zero_()
+    t0 = time.perf_counter()
+    _, r64 = G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws)
+    t_64 = time.perf_counter() - t0
+    assert r64.converged, r64.status_name
+    log(f"bench: float64 GMRES {t_64:.3f} s, {r64.iters} iters")
+    stride = args.fd_stride or 5 * m
+    smax = args.fd_max or -(-r64.iters // m) * m
+    sweep = []
+    for sw in range(0, smax + 1, stride):
+        x.zero_()
+        t0 = time.perf_counter()
+        _, both, first = G.gmres_fd_solve(A64, A32, b, sw, x, restart=m, tol=1e-10, max_iters=200000, ws=ws)
+        sec = time.perf_counter() - t0
+        row = {"switch": sw, "f32_iters": first.iters, "f64_iters": both.iters - first.iters,
+               "total_iters": both.iters, "seconds": round(sec, 4), "converged": both.converged,
+               "rel_res": both.rel_res,
+               "f64_start_rel_res": both.history[0] if both.history else None}
+        sweep.append(row)
+        log(f"bench: FD switch {sw}: {row['total_iters']} iters ({row['f32_iters']} f32), {sec:.3f} s, "
+            f"f64 start residual {row['f64_start_rel_res']:.3e}")
+    assert all(r["converged"] for r in sweep)
+    best = min(sweep, key=lambda r: r["seconds"])
+    x.zero_()
+    G.gmres_fd_solve(A64, A32, b, best["switch"], x, restart=m, tol=1e-10, max_iters=200000, ws=ws)
+    rel_fd = host_rel()
+    return {
+        "metric": METRIC, "value": round(t_ir, 5), "unit": "s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(t_ir * 1e3, 3), "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": desc, "n": prob.A.n, "nnz": prob.A.nnz, "restart": m, "tol": 1e-10,
+                   "fd_stride": stride, "fd_max": smax},
+        "ir_iters": rir[-1].iters, "ir_rel_res": rel_ir,
+        "fp64_gmres_s": round(t_64, 5), "fp64_iters": r64.iters, "ir_speedup_vs_fp64": round(t_64 / t_ir, 3),
+        "fd_best": {**best, "host_rel_res": rel_fd}, "ir_speedup_vs_best_fd": round(best["seconds"] / t_ir, 3),
+        "fd_sweep": sweep,
+        "roofline": {"kernel": "cgs_update_dots", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "launches": pr.prof_launches,
+                     "avg_launch_us": round(1e3 * pr.prof_ms / max(1, pr.prof_launches), 2)},
+    }
+
+
 def batch(args):
     import numpy as np
     import torch
@@ -421,11 +512,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace3d",
-                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor"])
+                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd"])
     ap.add_argument("--grid", type=int, default=0, help="grid side (0: the workload's own)")
     ap.add_argument("--restart", type=int, default=0, help="restart length (0: the workload's own)")
     ap.add_argument("--train", type=int, default=192, help="predictor: training systems")
     ap.add_argument("--test", type=int, default=64, help="predictor: held-out systems")
+    ap.add_argument("--fd-stride", type=int, default=0, help="fd: switch-point stride (0: 5 restarts)")
+    ap.add_argument("--fd-max", type=int, default=0, help="fd: last switch point (0: float64 GMRES's count)")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
@@ -456,6 +549,8 @@ def main():
         out = batch(args)
     elif args.workload == "predictor":
         out = predictor(args)
+    elif args.workload == "fd":
+        out = fd_sweep(args)
     else:
         out = single_system(args, args.workload)
     print(json.dumps(out), flush=True)

@@ -178,6 +178,31 @@ gmr_status gmres_ir_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly
                           const double* b, double* x, const gmr_params* params, void* ws,
                           size_t ws_bytes, gmr_result* result, double* hist, void* stream);
 
+/* Workspace (bytes, device) for gmres_fd_solve on a system of order n: the
+ * float64 solver's workspace plus float32 copies of b and of the iterate. */
+size_t gmres_fd_workspace_bytes(int32_t n, const gmr_params* params);
+
+/* GMRES-FD (§III-C, option 1; the switch-point study of §V-A): float32
+ * GMRES(m) on A32 from (float) x with right-hand side (float) b, for at most
+ * switch_iters iterations (fewer if its float32 explicit residual reaches tol
+ * or it stagnates by params->stagnation_cycles), then float64 GMRES(m) on A64
+ * from x = (double) of the float32 iterate until ||b - A64 x|| / ||b|| <= tol.
+ * switch_iters = 0 runs float64 GMRES(m) alone.  params->max_iters caps the
+ * iterations of both phases together and must exceed switch_iters; restart,
+ * tol, max_cycles, stagnation_cycles, prof_kernel and flags apply to each phase.
+ * A64, A32, b, x: as for gmres_ir_solve (b and x must be representable in
+ * float32).  result: both phases (cycles, iters, prof_* and history_len
+ * summed; status, rel_res and implicit_rel_res of the float64 phase; seconds
+ * over the whole call).  float_result: optional (NULL), the float32 phase alone;
+ * its residuals are float32 arithmetic against (float) b.  hist: optional host
+ * array of twice the capacity gmres_solve asks for: the float32 phase's
+ * relative residuals, then the float64 phase's.  If the float32 phase fails
+ * (e.g. GMR_ERR_NONFINITE), x is unchanged and both records describe that phase.
+ * ws: gmres_fd_workspace_bytes(n, params) bytes.  Synchronous. */
+gmr_status gmres_fd_solve(const gmr_csr* A64, const gmr_csr* A32, const double* b, double* x,
+                          const gmr_params* params, int64_t switch_iters, void* ws, size_t ws_bytes,
+                          gmr_result* result, gmr_result* float_result, double* hist, void* stream);
+
 /* out[k] = (float) in[k], round to nearest even; in, out: device.  Asynchronous. */
 gmr_status csr_values_to_f32(const double* in, float* out, int64_t count, void* stream);
 

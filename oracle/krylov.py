@@ -1,4 +1,4 @@
-"""Oracle: CSR SpMV, CGS2 Arnoldi, Givens least squares, GMRES(m), GMRES-IR.
+"""Oracle: CSR SpMV, CGS2 Arnoldi, Givens least squares, GMRES(m), GMRES-IR, GMRES-FD.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -263,3 +263,23 @@ def gmres_ir(A, b, x0, m: int, tol: float, max_iters: int,
     out.rel_res = gamma / bnorm
     out.converged = out.rel_res <= tol
     return out
+
+
+# ---------------------------------------------------------------------------
+# O5b: GMRES-FD (§III-C, option 1, the method of the switch-point study in
+# §V-A): GMRES(m) in float32 (float32 copies of A, b and x0) for
+# ``switch_iters`` iterations, then GMRES(m) in float64 started from the
+# float32 iterate widened to float64, until the float64 residual test holds.
+# ``max_iters`` caps both phases together.  Returns (float32 phase or None
+# when switch_iters is 0, float64 phase).
+# ---------------------------------------------------------------------------
+def gmres_fd(A, b, x0, m: int, tol: float, switch_iters: int, max_iters: int):
+    first = None
+    x = np.asarray(x0, dtype=np.float64)
+    used = 0
+    if switch_iters > 0:
+        first = gmres(A, b, x0, m, tol, switch_iters, dt=np.float32)
+        x = first.x.astype(np.float64)
+        used = first.iters
+    second = gmres(A, b, x, m, tol, max_iters - used, dt=np.float64)
+    return first, second

@@ -17,7 +17,7 @@ from . import _capi
 from ._capi import GMR_F32, GMR_F64, GmresError, PROF, check
 
 __all__ = ["DeviceCSR", "Poly", "SolveResult", "workspace_bytes", "alloc_workspace", "spmv",
-           "cgs2_orth", "poly_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve",
+           "cgs2_orth", "poly_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve", "gmres_fd_solve", "fd_workspace_bytes",
            "hessenberg_eigvals", "harmonic_ritz", "leja_order", "Batch", "GmresError", "GMR_F32", "GMR_F64", "lib"]
 
 
@@ -87,6 +87,16 @@ class DeviceCSR:
 def workspace_bytes(n: int, restart: int, dtype: int, with_poly: bool = False) -> int:
     p = _capi.gmr_params(restart, 1e-10, 1, 0, 0, 0, 0)
     nb = lib().gmres_workspace_bytes(n, C.byref(p), dtype, int(bool(with_poly)))
+    if nb == 0:
+        raise GmresError(-1, "invalid workspace query")
+    return int(nb)
+
+
+def fd_workspace_bytes(n: int, restart: int) -> int:
+    """Workspace bytes of gmres_fd_solve (also enough for gmres_solve and gmres_ir_solve
+    without a polynomial)."""
+    p = _capi.gmr_params(restart, 1e-10, 1, 0, 0, 0, 0)
+    nb = lib().gmres_fd_workspace_bytes(n, C.byref(p))
     if nb == 0:
         raise GmresError(-1, "invalid workspace query")
     return int(nb)
@@ -256,6 +266,34 @@ def gmres_ir_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, x: Optional[
                                   hist.ctypes.data_as(C.c_void_p), _stream(A64.device))
     check(status)
     return x, _result(res, hist)
+
+
+def gmres_fd_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, switch_iters: int,
+                   x: Optional[torch.Tensor] = None, *, restart: int = 50, tol: float = 1e-10,
+                   max_iters: int = 100000, max_cycles: int = 0, stagnation_cycles: int = 0,
+                   ws: Optional[torch.Tensor] = None, prof="none", graph: bool = False,
+                   persistent: bool = False):
+    """GMRES-FD: float32 GMRES(m) on A32 for switch_iters iterations, then float64
+    GMRES(m) on A64 from the float32 iterate.  Returns (x, result of both phases,
+    result of the float32 phase); the first history is the float64 phase's residuals,
+    the second the float32 phase's."""
+    if x is None:
+        x = torch.zeros_like(b)
+    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph, persistent)
+    if ws is None:
+        ws = alloc_workspace(fd_workspace_bytes(A64.n, restart), A64.device)
+    cap = max_cycles + 1 if max_cycles > 0 else 4096
+    hist = np.zeros(2 * cap)
+    res, res32 = _capi.gmr_result(), _capi.gmr_result()
+    s64, s32 = A64.struct(), A32.struct()
+    status = lib().gmres_fd_solve(C.byref(s64), C.byref(s32), _ptr(b), _ptr(x), C.byref(prm), int(switch_iters),
+                                  _ptr(ws), ws.numel(), C.byref(res), C.byref(res32),
+                                  hist.ctypes.data_as(C.c_void_p), _stream(A64.device))
+    check(status)
+    n1 = res32.history_len
+    both = _result(res, hist)
+    both.history = list(hist[n1: res.history_len])
+    return x, both, _result(res32, hist)
 
 
 def hessenberg_eigvals(H: np.ndarray) -> np.ndarray:

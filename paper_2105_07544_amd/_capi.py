@@ -22,7 +22,7 @@ PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_n
 # Every symbol include/gmres_ir.h declares.
 EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "poly_prec_apply",
             "poly_prec_destroy", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
-            "gmres_ir_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
+            "gmres_ir_solve", "gmres_fd_workspace_bytes", "gmres_fd_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
             "batch_set_tiling", "batch_set_graph", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve", "batch_gmres_solve",
             "batch_bcgs_step", "mlp_param_count", "mlp_workspace_bytes", "mlp_forward",
@@ -88,6 +88,12 @@ def load() -> C.CDLL:
     lib.gmres_ir_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P,
                                    C.POINTER(gmr_params), P, C.c_size_t, C.POINTER(gmr_result), P, P]
     lib.gmres_ir_solve.restype = st
+    lib.gmres_fd_workspace_bytes.argtypes = [C.c_int32, C.POINTER(gmr_params)]
+    lib.gmres_fd_workspace_bytes.restype = C.c_size_t
+    lib.gmres_fd_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, C.POINTER(gmr_params),
+                                   C.c_int64, P, C.c_size_t, C.POINTER(gmr_result), C.POINTER(gmr_result),
+                                   P, P]
+    lib.gmres_fd_solve.restype = st
     lib.csr_values_to_f32.argtypes = [P, P, C.c_int64, P]
     lib.csr_values_to_f32.restype = st
     lib.gmr_hessenberg_eigvals.argtypes = [C.c_int32, P, P, P]

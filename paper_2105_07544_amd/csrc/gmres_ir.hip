@@ -669,6 +669,88 @@ static gmr_status solve_impl(const SolveArgs& a) {
   return final_status;
 }
 
+
+// ---------------------------------------------------------------------------
+// GMRES-FD (§III-C, option 1): float32 GMRES(m) for a fixed number of
+// iterations, then float64 GMRES(m) started from the float32 iterate.  Both
+// phases are the plain solver above; the driver only adds the two casts.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void narrow_pair_kernel(int n, const double* __restrict__ b,
+                                                             const double* __restrict__ x,
+                                                             float* __restrict__ b32, float* __restrict__ x32) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    b32[i] = float(b[i]);
+    x32[i] = float(x[i]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void widen_kernel(int n, const float* __restrict__ in, double* __restrict__ out) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) out[i] = double(in[i]);
+}
+
+struct FdLayout {
+  size_t solver_end, b32, x32, end;
+};
+
+// The two phases share the solver workspace (sized for the larger, float64,
+// phase); the float32 copies of b and of the iterate follow it.
+static FdLayout fd_layout(int n, int m) {
+  const Small S = small_layout(n);
+  FdLayout L;
+  L.solver_end = std::max(big_layout(S.end, n, m, 8, 8, false).end, big_layout(S.end, n, m, 4, 4, false).end);
+  L.b32 = L.solver_end;
+  L.x32 = align_up(L.b32 + (size_t)n * 4, 256);
+  L.end = align_up(L.x32 + (size_t)n * 4, 256);
+  return L;
+}
+
+static gmr_status fd_solve(const gmr_csr* A64, const gmr_csr* A32, const double* b, double* x,
+                           const gmr_params* prm, int64_t switch_iters, void* ws, size_t ws_bytes,
+                           gmr_result* res, gmr_result* res32, double* hist, hipStream_t s) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const int n = A64->n;
+  const FdLayout L = fd_layout(n, prm->restart);
+  if (!ws || ws_bytes < L.end)
+    return fail(GMR_ERR_WORKSPACE, "gmres_fd_solve: workspace too small: need " + std::to_string(L.end) + " bytes");
+  float* b32 = (float*)((char*)ws + L.b32);
+  float* x32 = (float*)((char*)ws + L.x32);
+  gmr_result R1{};
+  R1.status = GMR_OK;
+  if (switch_iters > 0) {
+    narrow_pair_kernel<<<stream_grid(n), kBlock, 0, s>>>(n, b, x, b32, x32);
+    GMR_TRY(check_launch("narrow_pair_kernel"));
+    gmr_params p1 = *prm;
+    p1.max_iters = switch_iters;
+    SolveArgs a1{A32, A32, nullptr, b32, x32, &p1, ws, L.solver_end, &R1, hist, s};
+    const gmr_status st1 = solve_impl<float, float>(a1);
+    if (st1 < 0) {  // x is left as it was; both records describe phase one
+      R1.status = st1;
+      if (res32) *res32 = R1;
+      *res = R1;
+      return st1;
+    }
+    widen_kernel<<<stream_grid(n), kBlock, 0, s>>>(n, x32, x);
+    GMR_TRY(check_launch("widen_kernel"));
+  }
+  if (res32) *res32 = R1;
+  gmr_params p2 = *prm;
+  p2.max_iters = prm->max_iters - R1.iters;
+  gmr_result R2{};
+  SolveArgs a2{A64, A64, nullptr, b, x, &p2, ws, L.solver_end, &R2, hist ? hist + R1.history_len : nullptr, s};
+  const gmr_status st2 = solve_impl<double, double>(a2);
+  if (st2 < 0 && st2 != GMR_ERR_NONFINITE) return st2;
+  gmr_result R = R2;
+  R.cycles += R1.cycles;
+  R.iters += R1.iters;
+  R.history_len += R1.history_len;
+  R.prof_ms += R1.prof_ms;
+  R.prof_launches += R1.prof_launches;
+  R.prof_bytes += R1.prof_bytes;
+  R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  *res = R;
+  return st2;
+}
+
 }  // namespace gmr
 
 using namespace gmr;
@@ -886,6 +968,28 @@ gmr_status gmres_ir_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly
   GMR_TRY(solve_common_checks(params, b, x, result));
   SolveArgs a{A32, A64, P, b, x, params, ws, ws_bytes, result, hist, (hipStream_t)stream};
   return solve_impl<float, double>(a);
+}
+
+size_t gmres_fd_workspace_bytes(int32_t n, const gmr_params* params) {
+  if (n <= 0 || !params || params->restart < 1 || params->restart > kMaxCols) return 0;
+  return fd_layout(n, params->restart).end;
+}
+
+gmr_status gmres_fd_solve(const gmr_csr* A64, const gmr_csr* A32, const double* b, double* x,
+                          const gmr_params* params, int64_t switch_iters, void* ws, size_t ws_bytes,
+                          gmr_result* result, gmr_result* float_result, double* hist, void* stream) {
+  GMR_TRY(check_csr(A64, "gmres_fd_solve(A64)"));
+  GMR_TRY(check_csr(A32, "gmres_fd_solve(A32)"));
+  if (A64->dtype != GMR_F64 || A32->dtype != GMR_F32)
+    return fail(GMR_ERR_INVALID, "gmres_fd_solve: A64 must be float64 and A32 float32");
+  if (A64->n != A32->n || A64->nnz != A32->nnz)
+    return fail(GMR_ERR_INVALID, "gmres_fd_solve: A64 and A32 differ in size");
+  GMR_TRY(solve_common_checks(params, b, x, result));
+  if (switch_iters < 0) return fail(GMR_ERR_INVALID, "gmres_fd_solve: switch_iters < 0");
+  if (switch_iters >= params->max_iters)
+    return fail(GMR_ERR_INVALID, "gmres_fd_solve: max_iters must exceed switch_iters");
+  return fd_solve(A64, A32, b, x, params, switch_iters, ws, ws_bytes, result, float_result, hist,
+                  (hipStream_t)stream);
 }
 
 }  // extern "C"

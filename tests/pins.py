@@ -312,3 +312,47 @@ def check_arnoldi_f32_orthogonality():
 
 
 ALL_CHECKS.append(check_arnoldi_f32_orthogonality)
+
+
+# --- O5b GMRES-FD -------------------------------------------------------------
+def _dense(A):
+    D = np.zeros((A.n, A.n))
+    for r in range(A.n):
+        D[r, A.col_idx[A.row_ptr[r]:A.row_ptr[r + 1]]] = A.val[A.row_ptr[r]:A.row_ptr[r + 1]]
+    return D
+
+
+def check_gmres_fd():
+    # 2D Laplacian, n = 400, GMRES(10), b = A x_true
+    A = W.laplace2d(20)
+    D = _dense(A)
+    xt = rng(31).uniform(-1, 1, A.n)
+    b = D @ xt
+    bn = np.linalg.norm(b)
+    tol = 1e-10
+    kappa = np.linalg.cond(D)
+    x0 = np.zeros(A.n)
+    # switch 0: float64 GMRES(10) alone, which reaches the dense solution
+    f, s = O.gmres_fd(A, b, x0, 10, tol, 0, 5000)
+    assert f is None and s.converged and s.history[0] == 1.0
+    assert np.linalg.norm(b - D @ s.x) / bn <= tol
+    for sw in (40, 400):
+        f, s = O.gmres_fd(A, b, x0, 10, tol, sw, 5000)
+        # the float32 phase runs to the switch point: float32 cannot reach 1e-10
+        assert f.iters == sw and not f.converged
+        rf = np.linalg.norm(b - D @ f.x.astype(np.float64)) / bn
+        assert rf > 1e-9, f"float32 phase reached {rf}: not float32 arithmetic"
+        # the float64 phase starts from the widened float32 iterate
+        assert np.isclose(s.history[0], rf, rtol=1e-9, atol=0), (s.history[0], rf)
+        # and ends at the float64 tolerance, near the dense solution
+        assert s.converged and np.linalg.norm(b - D @ s.x) / bn <= tol
+        assert np.linalg.norm(s.x - xt) / np.linalg.norm(xt) <= 10 * kappa * tol
+        assert s.iters + f.iters <= 5000
+    # switching after the float32 phase has stalled: float32 iterations make no progress
+    f150, _ = O.gmres_fd(A, b, x0, 10, tol, 150, 5000)
+    r150 = np.linalg.norm(b - D @ f150.x.astype(np.float64)) / bn
+    r400 = np.linalg.norm(b - D @ f.x.astype(np.float64)) / bn
+    assert r400 > 0.1 * r150, (r150, r400)
+
+
+ALL_CHECKS.append(check_gmres_fd)

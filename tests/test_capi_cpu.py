@@ -84,6 +84,29 @@ def test_argument_errors_before_device_work():
     assert lib.spmv(C.byref(A), 5, 5, None) == -1
 
 
+def test_fd_host_checks_without_device():
+    lib = G.lib()
+    res, res32 = _capi.gmr_result(), _capi.gmr_result()
+    p = _capi.gmr_params(50, 1e-10, 100, 0, 0, 0, 0)
+    A64 = _capi.gmr_csr(10, 28, 16, 32, 48, 1)
+    A32 = _capi.gmr_csr(10, 28, 16, 32, 64, 0)
+    other = _capi.gmr_csr(11, 28, 16, 32, 64, 0)
+    nfd = lib.gmres_fd_workspace_bytes(1000, C.byref(p))
+    assert nfd > lib.gmres_workspace_bytes(1000, C.byref(p), 1, 0) >= lib.gmres_workspace_bytes(1000, C.byref(p), 0, 0)
+    assert lib.gmres_fd_workspace_bytes(1000, C.byref(_capi.gmr_params(0, 1e-10, 100, 0, 0, 0, 0))) == 0
+
+    def fd(a, b_, sw, prm=p, ws=None, nws=0):
+        return lib.gmres_fd_solve(C.byref(a), C.byref(b_), 8, 16, C.byref(prm), sw, ws, nws, C.byref(res),
+                                  C.byref(res32), None, None)
+    assert fd(A64, A64, 50) == -1 and b"float32" in lib.gmr_last_error()
+    assert fd(A64, other, 50) == -1 and b"differ" in lib.gmr_last_error()
+    assert fd(A64, A32, -1) == -1
+    assert fd(A64, A32, 100) == -1 and b"exceed" in lib.gmr_last_error()
+    assert fd(A64, A32, 50, ws=256, nws=16) == -3 and b"workspace" in lib.gmr_last_error()
+    assert lib.gmres_fd_solve(C.byref(A64), C.byref(A32), 8, 8, C.byref(p), 10, None, 0, C.byref(res),
+                              None, None, None) == -1
+
+
 def test_harmonic_ritz_matches_oracle():
     import workloads as W
     for A, d in ((W.convdiff2d(30, 0.05, W.configs.uniflow_wind), 10), (W.laplace2d(12), 7)):

@@ -101,6 +101,20 @@ def harmonic_unsquared(H, k):
 
 _orig_poly_apply = P.poly_apply
 
+
+def fd_phase2_from_x0(A, b, x0, m, tol, switch_iters, max_iters):
+    first = K.gmres(A, b, x0, m, tol, switch_iters, dt=np.float32) if switch_iters > 0 else None
+    second = K.gmres(A, b, np.asarray(x0, np.float64), m, tol,  # mistake: drops the float32 iterate
+                     max_iters - (first.iters if first else 0), dt=np.float64)
+    return first, second
+
+
+def fd_phase1_float64(A, b, x0, m, tol, switch_iters, max_iters):
+    first = K.gmres(A, b, x0, m, tol, switch_iters, dt=np.float64) if switch_iters > 0 else None  # mistake
+    x = first.x if first else np.asarray(x0, np.float64)
+    second = K.gmres(A, b, x, m, tol, max_iters - (first.iters if first else 0), dt=np.float64)
+    return first, second
+
 MUTATIONS = {
     "spmv_drop_last": ("spmv", spmv_drop_last),
     "spmv_row_index": ("spmv", spmv_row_index),
@@ -110,6 +124,8 @@ MUTATIONS = {
     "backsolve_transposed": ("back_substitute", backsolve_transposed),
     "poly_apply_half_a": ("poly_apply", poly_apply_half_a),
     "harmonic_unsquared": ("harmonic_ritz_values", harmonic_unsquared),
+    "fd_phase2_from_x0": ("gmres_fd", fd_phase2_from_x0),
+    "fd_phase1_float64": ("gmres_fd", fd_phase1_float64),
 }
 
 FAST_CHECKS = [c for c in pins.ALL_CHECKS if c.__name__ not in

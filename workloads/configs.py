@@ -16,7 +16,7 @@ import numpy as np
 from .prng import uniform01, uniform_pm1, uniform_int
 from .stencils import CSR, laplace2d, laplace3d, convdiff2d
 
-__all__ = ["Problem", "host_matvec", "config1_laplace2d", "config2_laplace3d",
+__all__ = ["Problem", "host_matvec", "config1_laplace2d", "config2_laplace3d", "fd_laplace3d",
            "config3_convdiff", "config4_batch", "random_rhs", "poly_start_vector", "block_diag",
            "stack_rows", "config5_systems"]
 
@@ -59,6 +59,13 @@ def config2_laplace3d(N: int = 150, seed: int = 2, restart: int = 50) -> Problem
     A = laplace3d(N)
     x_true = uniform_pm1(seed, A.n)
     return Problem(f"laplace3d_N{N}", A, host_matvec(A, x_true), x_true, restart, 0, "f32")
+
+
+def fd_laplace3d(N: int = 200, restart: int = 50) -> Problem:
+    """The GMRES-FD switch-point problem of §V-A: 3D Laplacian 6/-1 on N^3, b = ones
+    and x0 = 0 (the right-hand side and start vector of every experiment, §V)."""
+    A = laplace3d(N)
+    return Problem(f"laplace3d_N{N}_ones", A, np.ones(A.n), None, restart, 0, "f32")
 
 
 def uniflow_wind(x, y):
