@@ -18,6 +18,8 @@ Other workloads (each prints its own line; the default line is the one above):
              compare held-out time to solution with the fixed (m=50, d=0, f32)
   fd         GMRES-FD switch-point sweep on the 3D Laplacian 200^3 (b = ones):
              float32 GMRES(50) for s iterations, then float64 GMRES(50)
+  prec32     polynomial degrees 10..70 on the same Laplacian: float64 GMRES with
+             a float64 or a float32 polynomial (loss of accuracy), and GMRES-IR
 
 Extra fields: the float64 GMRES time on the same GPU and the ratio,
 per-kernel-family time and GB/s (the analogue of the paper's Table I), the
@@ -255,6 +257,15 @@ def single_system(args, kind):
     t_64 = (time.perf_counter() - t0) / len(r64)
     assert all(r.converged for r in r64), [r.status_name for r in r64]
 
+    mixed = None
+    if degree:
+        # the middle option of §V-C: float64 GMRES with the float32 polynomial
+        log("bench: float64 GMRES with the float32 polynomial")
+        x.zero_()
+        t0 = time.perf_counter()
+        _, rmx = G.gmres_f32prec_solve(A64, A32, P32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_64)
+        mixed = {"seconds": round(time.perf_counter() - t0, 5), "status": rmx.status_name, "iters": rmx.iters,
+                 "loss_of_accuracy": rmx.loss_of_accuracy}
     breakdown = {}
     if not args.no_breakdown:
         log("bench: per-kernel breakdown")
@@ -280,6 +291,7 @@ def single_system(args, kind):
         "rel_res": rel, "forward_error": fwd,
         "ms_per_step_unprofiled": round(1e3 * float(np.median(unprof)), 3) if unprof else None,
         "graph": graph, "persistent_cycle": pers,
+        **({"fp64_gmres_f32poly": mixed} if mixed else {}),
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": stored_traffic(dominant, kind), "launches": prof_launches,
@@ -292,7 +304,9 @@ def single_system(args, kind):
         prec32, ks = None, (1, 4, 10)
         import oracle as O
         if degree:
-            roots = P32.roots()
+            # the oracle builds its own float32 polynomial from the same start vector
+            v0 = W.poly_start_vector(prob.A.n, prob.poly_seed).astype(np.float32)
+            roots = O.poly_roots(prob.A, degree, v0, np.float32)
             prec32 = lambda v: O.poly_apply(prob.A, roots, v, np.float32)  # noqa: E731
             ks = (1, 2, 3)
         out["cpu_baseline"] = cpu_baseline(prob, last.cycles, m, prec32, ks)
@@ -385,6 +399,75 @@ def fd_sweep(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launches": pr.prof_launches,
                      "avg_launch_us": round(1e3 * pr.prof_ms / max(1, pr.prof_launches), 2)},
+    }
+
+
+def prec32_sweep(args):
+    """§V-F: float64 GMRES(m) on the 3D Laplacian 200^3 (b = ones) with a GMRES
+    polynomial of degree 10..70 built and applied in float64, or built and applied
+    in float32 (corrected by restarting from the explicit residual after a loss of
+    accuracy, or stopped there), beside GMRES-IR with the float32 polynomial."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07544_amd as G
+    import workloads as W
+
+    dev = "cuda:0"
+    N = args.grid or 200
+    log("bench: building the workload")
+    prob = W.fd_laplace3d(N, restart=args.restart or 50)
+    m = prob.restart
+    A64 = G.DeviceCSR.from_host(prob.A, dev)
+    A32 = A64.to_f32()
+    b = torch.from_numpy(prob.b).to(dev)
+    x = torch.zeros_like(b)
+    ws = G.alloc_workspace(G.workspace_bytes(prob.A.n, m, G.GMR_F64, True), dev)
+    v0 = W.poly_start_vector(prob.A.n, 0)
+    Ah = host_csr(prob.A)
+    degrees = [int(d) for d in args.degrees.split(",")]
+    rows = []
+    cap = 5000   # iterations; a float32 polynomial that cannot reach 1e-10 also stops after 20 stagnant restarts
+
+    def run(fn):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, r = fn()
+        sec = time.perf_counter() - t0
+        xh = x.cpu().numpy()
+        rel = float(np.linalg.norm(prob.b - Ah @ xh) / np.linalg.norm(prob.b))
+        return {"status": r.status_name, "iters": r.iters, "cycles": r.cycles, "seconds": round(sec, 4),
+                "rel_res": rel, "loss_of_accuracy": r.loss_of_accuracy}
+
+    for d in degrees:
+        log(f"bench: degree {d}: polynomial setup (outside the timed solves)")
+        P64 = G.poly_prec_setup(A64, d, torch.from_numpy(v0).to(dev))
+        P32 = G.poly_prec_setup(A32, d, torch.from_numpy(v0.astype(np.float32)).to(dev))
+        row = {"degree": d}
+        row["f64_f64poly"] = run(lambda: G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=cap, ws=ws, P=P64))
+        row["f64_f32poly"] = run(lambda: G.gmres_f32prec_solve(A64, A32, P32, b, x, restart=m, tol=1e-10,
+                                                               max_iters=cap, stagnation_cycles=20, ws=ws))
+        row["f64_f32poly_stop_on_loss"] = run(lambda: G.gmres_f32prec_solve(A64, A32, P32, b, x, restart=m,
+                                                                            tol=1e-10, max_iters=cap, ws=ws,
+                                                                            stop_on_loss=True))
+        row["ir_f32poly"] = run(lambda: G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=cap,
+                                                         stagnation_cycles=20, ws=ws, P=P32))
+        rows.append(row)
+        log("bench: " + json.dumps(row))
+        del P64, P32
+    best_ir = min(r["ir_f32poly"]["seconds"] for r in rows if r["ir_f32poly"]["status"] == "GMR_OK")
+    best_64 = min(r["f64_f64poly"]["seconds"] for r in rows if r["f64_f64poly"]["status"] == "GMR_OK")
+    return {
+        "metric": METRIC, "value": round(best_ir, 5), "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": round(best_ir * 1e3, 3), "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": (f"polynomial degree sweep {degrees}: float64 GMRES({m}) with a float64 or a "
+                                f"float32 GMRES polynomial, GMRES({m})-IR with the float32 one; 3D Laplacian "
+                                f"6/-1 on {N}^3 (n={prob.A.n}), b=ones, x0=0, tol 1e-10"),
+                   "n": prob.A.n, "nnz": prob.A.nnz, "restart": m, "tol": 1e-10},
+        "best_fp64_f64poly_s": round(best_64, 5), "ir_speedup_vs_best_fp64": round(best_64 / best_ir, 3),
+        "sweep": rows,
     }
 
 
@@ -512,13 +595,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace3d",
-                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd"])
+                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd", "prec32"])
     ap.add_argument("--grid", type=int, default=0, help="grid side (0: the workload's own)")
     ap.add_argument("--restart", type=int, default=0, help="restart length (0: the workload's own)")
     ap.add_argument("--train", type=int, default=192, help="predictor: training systems")
     ap.add_argument("--test", type=int, default=64, help="predictor: held-out systems")
     ap.add_argument("--fd-stride", type=int, default=0, help="fd: switch-point stride (0: 5 restarts)")
     ap.add_argument("--fd-max", type=int, default=0, help="fd: last switch point (0: float64 GMRES's count)")
+    ap.add_argument("--degrees", default="10,20,30,40,50,60,70", help="prec32: polynomial degrees")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
@@ -551,6 +635,8 @@ def main():
         out = predictor(args)
     elif args.workload == "fd":
         out = fd_sweep(args)
+    elif args.workload == "prec32":
+        out = prec32_sweep(args)
     else:
         out = single_system(args, args.workload)
     print(json.dumps(out), flush=True)

@@ -43,6 +43,8 @@ typedef enum {
   GMR_OK = 0,
   GMR_NOT_CONVERGED = 1,     /* max_iters / max_cycles reached; x = last iterate        */
   GMR_STAGNATED = 2,         /* no residual decrease over `stagnation_cycles` restarts */
+  GMR_LOSS_OF_ACCURACY = 3,  /* GMR_FLAG_STOP_ON_LOSS: the implicit residual met tol, the
+                                explicit one did not (§V-F); x = last iterate             */
   GMR_ERR_INVALID = -1,      /* bad argument (null pointer, size, dtype mismatch, ...)   */
   GMR_ERR_HIP = -2,          /* a HIP call failed                                        */
   GMR_ERR_WORKSPACE = -3,    /* workspace smaller than gmres_workspace_bytes()           */
@@ -90,6 +92,13 @@ typedef struct {
  * polynomial, profiling, GMR_FLAG_GRAPH); the arithmetic is the same, summed
  * in a different grouping. */
 #define GMR_FLAG_PERSISTENT 2
+/* gmr_params.flags: plain GMRES (gmres_solve, gmres_f32prec_solve, the float64
+ * phase of gmres_fd_solve) ends with GMR_LOSS_OF_ACCURACY at the first restart
+ * whose cycle signalled convergence through its implicit residual while the
+ * explicit residual ||b - A x|| / ||b|| was above tol (§V-F).  Without the flag
+ * the solver counts such a restart in result->loss_of_accuracy and goes on
+ * from the explicit residual: the correction §V-F proposes.  GMRES-IR ignores it. */
+#define GMR_FLAG_STOP_ON_LOSS 4
 
 typedef struct {
   int32_t status;            /* gmr_status                                                 */
@@ -99,7 +108,9 @@ typedef struct {
   double implicit_rel_res;   /* |g_{k+1}| * gamma / ||b|| of the last cycle                */
   double seconds;            /* wall time of the solve (host clock, stream synchronised)   */
   int32_t history_len;       /* entries written to `hist`                                  */
-  int32_t reserved;
+  int32_t loss_of_accuracy;  /* gmres_solve, gmres_f32prec_solve, gmres_fd_solve: restarts
+                                whose cycle ended on its implicit residual (or a breakdown)
+                                while the explicit residual was still above tol (§V-F)     */
   double prof_ms;            /* summed duration of the profiled launches                   */
   int64_t prof_launches;     /* number of profiled launches                                */
   double prof_bytes;         /* summed algorithmic bytes of the profiled launches          */
@@ -110,8 +121,9 @@ typedef struct gmr_poly gmr_poly;  /* opaque, host-side: the roots of the polyno
 /* Workspace (bytes, device) needed by gmres_solve / gmres_ir_solve for a system of
  * order n with the given parameters and working precision `dtype` (F64: plain
  * float64 GMRES; F32: GMRES-IR, or a float32-only gmres_solve), with a
- * polynomial preconditioner when `with_poly` != 0.  Also valid for cgs2_orth
- * (with restart >= k) and for poly_prec_setup/poly_prec_apply. */
+ * polynomial preconditioner when `with_poly` != 0 (F64 with a polynomial also
+ * covers gmres_f32prec_solve).  Also valid for cgs2_orth (with restart >= k)
+ * and for poly_prec_setup/poly_prec_apply. */
 size_t gmres_workspace_bytes(int32_t n, const gmr_params* params, int32_t dtype, int32_t with_poly);
 
 /* y = A x (§V-D: y_i = sum_k val[k] x[col[k]], summed in ascending k; products
@@ -135,7 +147,7 @@ gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t
  * (n entries of A's dtype, need not be normalised) in A's precision, take the
  * harmonic Ritz values (the roots of the GMRES residual polynomial), order
  * them by the modified Leja ordering and round them to A's precision.  A
- * lucky breakdown after s steps lowers the degree to s-1.  0 <= degree <= 64.
+ * lucky breakdown after s steps lowers the degree to s-1.  0 <= degree <= 128.
  * Synchronous; *out must be released with poly_prec_destroy. */
 gmr_status poly_prec_setup(const gmr_csr* A, int32_t degree, const void* v0, void* ws,
                            size_t ws_bytes, gmr_poly** out, void* stream);
@@ -177,6 +189,20 @@ gmr_status gmres_solve(const gmr_csr* A, const gmr_poly* P, const void* b, void*
 gmr_status gmres_ir_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly* P,
                           const double* b, double* x, const gmr_params* params, void* ws,
                           size_t ws_bytes, gmr_result* result, double* hist, void* stream);
+
+/* Float64 GMRES(m) with a float32 right preconditioner (§III-D option (a), the
+ * middle option of the comparison in §V-C and the study of §V-F): the solver
+ * is gmres_solve in float64 on A64, and each application of M = p(A32) casts
+ * its float64 input to float32, applies the float32 polynomial P32 (built by
+ * poly_prec_setup on A32) with A32's products in float32, and widens the
+ * result back to float64.  Loss of accuracy (§V-F) is counted in
+ * result->loss_of_accuracy and corrected by restarting from the explicit
+ * residual, or ends the solve under GMR_FLAG_STOP_ON_LOSS.  b, x: device
+ * float64; hist as for gmres_solve; ws: gmres_workspace_bytes(n, params,
+ * GMR_F64, 1) bytes.  Synchronous. */
+gmr_status gmres_f32prec_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly* P32, const double* b,
+                               double* x, const gmr_params* params, void* ws, size_t ws_bytes,
+                               gmr_result* result, double* hist, void* stream);
 
 /* Workspace (bytes, device) for gmres_fd_solve on a system of order n: the
  * float64 solver's workspace plus float32 copies of b and of the iterate. */

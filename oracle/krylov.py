@@ -130,6 +130,8 @@ class GmresOutcome:
     implicit_rel_res: float = float("nan")
     history: List[float] = field(default_factory=list)   # explicit rel. residual per restart
     implicit_history: List[float] = field(default_factory=list)  # |g_{j+1}|/||b|| per iteration
+    loss_of_accuracy: int = 0         # restarts whose cycle met tol implicitly but not explicitly
+    stopped_on_loss: bool = False
 
 
 def _explicit_rel_res(A, b, x):
@@ -142,11 +144,13 @@ def _explicit_rel_res(A, b, x):
 # The implicit residual |g_{j+1}| is tested after every iteration so that a
 # cycle may stop early (§III-B contrasts this with GMRES-IR); convergence is
 # then confirmed with the explicit residual, and a false signal (the loss of
-# accuracy of §V-F) simply leads to another restart.
+# accuracy of §V-F) is counted and simply leads to another restart, or ends
+# the solve when ``stop_on_loss`` is set.
 # Right preconditioning (§III-D): w = A M v_j and the correction is M V y.
 # ---------------------------------------------------------------------------
 def gmres(A, b, x0, m: int, tol: float, max_iters: int, dt=np.float64,
-          prec: Optional[Callable] = None, max_cycles: Optional[int] = None) -> GmresOutcome:
+          prec: Optional[Callable] = None, max_cycles: Optional[int] = None,
+          stop_on_loss: bool = False) -> GmresOutcome:
     n = A.n
     b_w = np.asarray(b).astype(dt)
     bnorm = float(np.linalg.norm(np.asarray(b, dtype=np.float64)))
@@ -167,6 +171,7 @@ def gmres(A, b, x0, m: int, tol: float, max_iters: int, dt=np.float64,
         V[:, 0] = r / gamma
         g[0] = float(gamma)
         k = 0
+        signalled = False
         for j in range(m):
             z = prec(V[:, j]) if prec else V[:, j]
             w = spmv(A, z, dt)
@@ -180,7 +185,8 @@ def gmres(A, b, x0, m: int, tol: float, max_iters: int, dt=np.float64,
             brk = _is_breakdown(beta, dt)
             if not brk:
                 V[:, j + 1] = w / beta
-            if res / bnorm <= tol or brk or it >= max_iters:
+            signalled = res / bnorm <= tol or brk
+            if signalled or it >= max_iters:
                 break
         y = back_substitute(H[:k, :k], g[:k])
         u = V[:, :k] @ y.astype(dt)
@@ -198,6 +204,11 @@ def gmres(A, b, x0, m: int, tol: float, max_iters: int, dt=np.float64,
             break
         if not np.isfinite(rel):
             break
+        if signalled:   # implicit convergence that the explicit residual does not confirm
+            out.loss_of_accuracy += 1
+            if stop_on_loss:
+                out.stopped_on_loss = True
+                break
     out.x, out.iters, out.cycles = x, it, cycles
     out.rel_res = out.history[-1]
     return out
@@ -283,3 +294,12 @@ def gmres_fd(A, b, x0, m: int, tol: float, switch_iters: int, max_iters: int):
         used = first.iters
     second = gmres(A, b, x, m, tol, max_iters - used, dt=np.float64)
     return first, second
+
+
+# ---------------------------------------------------------------------------
+# O5c: a float32 preconditioner inside float64 GMRES (§III-D option (a)): each
+# application casts its float64 input to float32, applies M in float32 and
+# casts the result back to float64.
+# ---------------------------------------------------------------------------
+def cast_wrapped(prec32: Callable) -> Callable:
+    return lambda v: np.asarray(prec32(np.asarray(v).astype(np.float32)), dtype=np.float32).astype(np.float64)

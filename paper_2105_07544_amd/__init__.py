@@ -17,7 +17,8 @@ from . import _capi
 from ._capi import GMR_F32, GMR_F64, GmresError, PROF, check
 
 __all__ = ["DeviceCSR", "Poly", "SolveResult", "workspace_bytes", "alloc_workspace", "spmv",
-           "cgs2_orth", "poly_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve", "gmres_fd_solve", "fd_workspace_bytes",
+           "cgs2_orth", "poly_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_solve",
+           "fd_workspace_bytes",
            "hessenberg_eigvals", "harmonic_ritz", "leja_order", "Batch", "GmresError", "GMR_F32", "GMR_F64", "lib"]
 
 
@@ -204,14 +205,17 @@ class SolveResult:
     prof_ms: float = 0.0
     prof_launches: int = 0
     prof_bytes: float = 0.0
+    loss_of_accuracy: int = 0
 
     @property
     def converged(self) -> bool:
         return self.status == 0
 
 
-def _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph=False, persistent=False):
-    flags = (_capi.GMR_FLAG_GRAPH if graph else 0) | (_capi.GMR_FLAG_PERSISTENT if persistent else 0)
+def _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph=False, persistent=False,
+            stop_on_loss=False):
+    flags = ((_capi.GMR_FLAG_GRAPH if graph else 0) | (_capi.GMR_FLAG_PERSISTENT if persistent else 0)
+             | (_capi.GMR_FLAG_STOP_ON_LOSS if stop_on_loss else 0))
     return _capi.gmr_params(int(restart), float(tol), int(max_iters), int(max_cycles),
                             int(stagnation_cycles), PROF[prof] if isinstance(prof, str) else int(prof), flags)
 
@@ -220,18 +224,19 @@ def _result(res: _capi.gmr_result, hist: np.ndarray) -> SolveResult:
     return SolveResult(res.status, _capi.STATUS.get(res.status, str(res.status)), int(res.iters),
                        int(res.cycles), float(res.rel_res), float(res.implicit_rel_res),
                        float(res.seconds), list(hist[: res.history_len]), float(res.prof_ms),
-                       int(res.prof_launches), float(res.prof_bytes))
+                       int(res.prof_launches), float(res.prof_bytes), int(res.loss_of_accuracy))
 
 
 def gmres_solve(A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None, *, restart: int = 50,
                 tol: float = 1e-10, max_iters: int = 100000, max_cycles: int = 0,
                 P: Optional[Poly] = None, ws: Optional[torch.Tensor] = None, prof="none",
-                graph: bool = False, persistent: bool = False):
+                graph: bool = False, persistent: bool = False, stop_on_loss: bool = False):
     """Restarted GMRES(m) in A's precision.  x (x0, updated in place) defaults to 0.
-    persistent: one single-block kernel per restart cycle for small systems."""
+    persistent: one single-block kernel per restart cycle for small systems.
+    stop_on_loss: end at the first loss of accuracy instead of restarting."""
     if x is None:
         x = torch.zeros_like(b)
-    prm = _params(restart, tol, max_iters, max_cycles, 0, prof, graph, persistent)
+    prm = _params(restart, tol, max_iters, max_cycles, 0, prof, graph, persistent, stop_on_loss)
     if ws is None:
         ws = alloc_workspace(workspace_bytes(A.n, restart, A.dtype, P is not None), A.device)
     cap = max_cycles + 1 if max_cycles > 0 else 4096
@@ -268,18 +273,41 @@ def gmres_ir_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, x: Optional[
     return x, _result(res, hist)
 
 
+def gmres_f32prec_solve(A64: DeviceCSR, A32: DeviceCSR, P32: Poly, b: torch.Tensor,
+                        x: Optional[torch.Tensor] = None, *, restart: int = 50, tol: float = 1e-10,
+                        max_iters: int = 100000, max_cycles: int = 0, stagnation_cycles: int = 0,
+                        ws: Optional[torch.Tensor] = None, prof="none", graph: bool = False,
+                        stop_on_loss: bool = False):
+    """Float64 GMRES(m) on A64 with the float32 polynomial P32 (built on A32) as right
+    preconditioner: each application casts to float32, applies p(A32), widens back."""
+    if x is None:
+        x = torch.zeros_like(b)
+    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph, False, stop_on_loss)
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(A64.n, restart, GMR_F64, True), A64.device)
+    cap = max_cycles + 1 if max_cycles > 0 else 4096
+    hist = np.zeros(cap)
+    res = _capi.gmr_result()
+    s64, s32 = A64.struct(), A32.struct()
+    status = lib().gmres_f32prec_solve(C.byref(s64), C.byref(s32), P32.handle, _ptr(b), _ptr(x), C.byref(prm),
+                                       _ptr(ws), ws.numel(), C.byref(res), hist.ctypes.data_as(C.c_void_p),
+                                       _stream(A64.device))
+    check(status)
+    return x, _result(res, hist)
+
+
 def gmres_fd_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, switch_iters: int,
                    x: Optional[torch.Tensor] = None, *, restart: int = 50, tol: float = 1e-10,
                    max_iters: int = 100000, max_cycles: int = 0, stagnation_cycles: int = 0,
                    ws: Optional[torch.Tensor] = None, prof="none", graph: bool = False,
-                   persistent: bool = False):
+                   persistent: bool = False, stop_on_loss: bool = False):
     """GMRES-FD: float32 GMRES(m) on A32 for switch_iters iterations, then float64
     GMRES(m) on A64 from the float32 iterate.  Returns (x, result of both phases,
     result of the float32 phase); the first history is the float64 phase's residuals,
     the second the float32 phase's."""
     if x is None:
         x = torch.zeros_like(b)
-    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph, persistent)
+    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph, persistent, stop_on_loss)
     if ws is None:
         ws = alloc_workspace(fd_workspace_bytes(A64.n, restart), A64.device)
     cap = max_cycles + 1 if max_cycles > 0 else 4096

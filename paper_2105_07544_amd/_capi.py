@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(HERE, "libgmresir.so")
 GMR_F32, GMR_F64 = 0, 1
 GMR_FLAG_GRAPH = 1
 GMR_FLAG_PERSISTENT = 2
-STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", -1: "GMR_ERR_INVALID",
+GMR_FLAG_STOP_ON_LOSS = 4
+STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", 3: "GMR_LOSS_OF_ACCURACY", -1: "GMR_ERR_INVALID",
           -2: "GMR_ERR_HIP", -3: "GMR_ERR_WORKSPACE", -4: "GMR_ERR_NONFINITE",
           -5: "GMR_ERR_UNSUPPORTED"}
 PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_norm": 4,
@@ -22,7 +23,7 @@ PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_n
 # Every symbol include/gmres_ir.h declares.
 EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "poly_prec_apply",
             "poly_prec_destroy", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
-            "gmres_ir_solve", "gmres_fd_workspace_bytes", "gmres_fd_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
+            "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_workspace_bytes", "gmres_fd_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
             "batch_set_tiling", "batch_set_graph", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve", "batch_gmres_solve",
             "batch_bcgs_step", "mlp_param_count", "mlp_workspace_bytes", "mlp_forward",
@@ -43,7 +44,7 @@ class gmr_params(C.Structure):
 class gmr_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("cycles", C.c_int32), ("iters", C.c_int64),
                 ("rel_res", C.c_double), ("implicit_rel_res", C.c_double),
-                ("seconds", C.c_double), ("history_len", C.c_int32), ("reserved", C.c_int32),
+                ("seconds", C.c_double), ("history_len", C.c_int32), ("loss_of_accuracy", C.c_int32),
                 ("prof_ms", C.c_double), ("prof_launches", C.c_int64),
                 ("prof_bytes", C.c_double)]
 
@@ -88,6 +89,9 @@ def load() -> C.CDLL:
     lib.gmres_ir_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P,
                                    C.POINTER(gmr_params), P, C.c_size_t, C.POINTER(gmr_result), P, P]
     lib.gmres_ir_solve.restype = st
+    lib.gmres_f32prec_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P,
+                                        C.POINTER(gmr_params), P, C.c_size_t, C.POINTER(gmr_result), P, P]
+    lib.gmres_f32prec_solve.restype = st
     lib.gmres_fd_workspace_bytes.argtypes = [C.c_int32, C.POINTER(gmr_params)]
     lib.gmres_fd_workspace_bytes.restype = C.c_size_t
     lib.gmres_fd_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, C.POINTER(gmr_params),

@@ -88,7 +88,7 @@ static Small small_layout(int n) {
 }
 
 struct Big {
-  size_t V, W0, W1, R, U, P0, P1, Tt, Z, end;
+  size_t V, W0, W1, R, U, P0, P1, Tt, Z, X32, Y32, end;
   int64_t ldv;
 };
 
@@ -103,12 +103,18 @@ static Big big_layout(size_t base, int n, int m, size_t s, size_t so, bool poly)
   L.W1 = take((size_t)n * s);
   L.R = take((size_t)n * so);
   L.U = take((size_t)n * s);
-  L.P0 = L.P1 = L.Tt = L.Z = 0;
+  L.P0 = L.P1 = L.Tt = L.Z = L.X32 = L.Y32 = 0;
   if (poly) {
     L.P0 = take((size_t)n * s);
     L.P1 = take((size_t)n * s);
     L.Tt = take((size_t)n * s);
     L.Z = take((size_t)n * s);
+    if (s == 8) {
+      // a float32 polynomial inside float64 GMRES: float32 copies of its input
+      // and output (P0, P1 and Tt then hold its float32 work vectors)
+      L.X32 = take((size_t)n * 4);
+      L.Y32 = take((size_t)n * 4);
+    }
   }
   L.end = o;
   return L;
@@ -429,6 +435,7 @@ struct SolveArgs {
   gmr_result* res;
   double* hist;
   hipStream_t stream;
+  const gmr_csr* Aprec = nullptr;  // matrix of the polynomial's products (null: Ain)
 };
 
 static gmr_status check_params(const gmr_params* p) {
@@ -473,6 +480,14 @@ struct CycleGraph {
   }
 };
 
+// out = (To) in, skipped once the cycle has ended (done set).
+template <class From, class To>
+__global__ __launch_bounds__(kBlock) void cast_vec_kernel(int n, const From* __restrict__ in, To* __restrict__ out,
+                                                          const int* __restrict__ done) {
+  if (done && *done) return;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) out[i] = To(in[i]);
+}
+
 gmr_status library_stream(hipStream_t* out) {
   static thread_local hipStream_t streams[64] = {};
   int dev = 0;
@@ -491,6 +506,10 @@ static gmr_status solve_impl(const SolveArgs& a) {
   const int m = prm.restart;
   const bool implicit_stop = sizeof(TI) == sizeof(TO);  // plain GMRES
   const bool poly = a.P != nullptr;
+  // §III-D option (a): a float32 polynomial applied inside float64 GMRES, to
+  // float32 copies of its input, the result widened back to float64
+  const bool mixed = poly && a.P->dtype == GMR_F32 && sizeof(TI) == 8;
+  const gmr_csr* Ap = a.Aprec ? a.Aprec : a.Ain;
   Ws ws{(char*)a.ws, small_layout(n)};
   const Big B = big_layout(ws.S.end, n, m, sizeof(TI), sizeof(TO), poly);
   if (!a.ws || a.ws_bytes < B.end)
@@ -567,6 +586,19 @@ static gmr_status solve_impl(const SolveArgs& a) {
   }
   double gamma = st.gamma;
   push_hist(gamma / bnorm);
+  // z = p(A) v in the polynomial's precision
+  auto apply_prec = [&](const TI* in, TI* out, const int* dn) -> gmr_status {
+    if (!mixed)
+      return poly_apply_impl<TI>(c, a.P, Ap, in, out, ws.at<TI>(B.P0), ws.at<TI>(B.P1), ws.at<TI>(B.Tt), dn);
+    float* x32 = ws.at<float>(B.X32);
+    float* y32 = ws.at<float>(B.Y32);
+    cast_vec_kernel<TI, float><<<stream_grid(n), kBlock, 0, c.s>>>(n, in, x32, dn);
+    GMR_TRY(check_launch("cast_vec_kernel"));
+    GMR_TRY(poly_apply_impl<float>(c, a.P, Ap, x32, y32, ws.at<float>(B.P0), ws.at<float>(B.P1),
+                                   ws.at<float>(B.Tt), dn));
+    cast_vec_kernel<float, TI><<<stream_grid(n), kBlock, 0, c.s>>>(n, y32, out, dn);
+    return check_launch("cast_vec_kernel");
+  };
   // Everything one restart cycle enqueues: the cast of r, mc inner iterations,
   // the solution update and the next residual (with its norm).
   auto enqueue_cycle = [&](int mc) -> gmr_status {
@@ -583,8 +615,7 @@ static gmr_status solve_impl(const SolveArgs& a) {
         TI* Z = ws.at<TI>(B.Z);
         scale_kernel<TI><<<stream_grid(n), kBlock, 0, c.s>>>(n, W[cur], cs.inv_beta, vj, done);
         GMR_TRY(check_launch("scale_kernel"));
-        GMR_TRY(poly_apply_impl<TI>(c, a.P, a.Ain, vj, Z, ws.at<TI>(B.P0), ws.at<TI>(B.P1),
-                                    ws.at<TI>(B.Tt), done));
+        GMR_TRY(apply_prec(vj, Z, done));
         GMR_TRY(launch_spmv<TI>(c, a.Ain, Z, nullptr, nullptr, wn, done));
       } else {
         GMR_TRY(launch_spmv<TI>(c, a.Ain, W[cur], cs.inv_beta, vj, wn, done));
@@ -596,8 +627,7 @@ static gmr_status solve_impl(const SolveArgs& a) {
       TI* Z = ws.at<TI>(B.Z);
       solution_update_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, V, B.ldv, cs.y, st_dev, U, nullptr);
       GMR_TRY(check_launch("solution_update_kernel"));
-      GMR_TRY(poly_apply_impl<TI>(c, a.P, a.Ain, U, Z, ws.at<TI>(B.P0), ws.at<TI>(B.P1),
-                                  ws.at<TI>(B.Tt), nullptr));
+      GMR_TRY(apply_prec(U, Z, nullptr));
       axpy_gamma_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, Z, st_dev, x);
       GMR_TRY(check_launch("axpy_gamma_kernel"));
     } else {
@@ -647,6 +677,13 @@ static gmr_status solve_impl(const SolveArgs& a) {
     gamma = st.gamma;
     push_hist(gamma / bnorm);
     if (st.nonfinite) { final_status = GMR_ERR_NONFINITE; fail(GMR_ERR_NONFINITE, "non-finite value in the Hessenberg problem"); break; }
+    // §V-F: the cycle ended on its implicit residual (or a breakdown) but the
+    // explicit one is above tol.  The next restart starts from the explicit
+    // residual, which corrects it, unless the caller asked to stop here.
+    if (implicit_stop && st.done && gamma / bnorm > prm.tol) {
+      R.loss_of_accuracy += 1;
+      if (prm.flags & GMR_FLAG_STOP_ON_LOSS) { final_status = GMR_LOSS_OF_ACCURACY; break; }
+    }
   }
   GMR_HIP(hipStreamSynchronize(c.s));
   const auto t_end = std::chrono::steady_clock::now();
@@ -682,10 +719,6 @@ __global__ __launch_bounds__(kBlock) void narrow_pair_kernel(int n, const double
     b32[i] = float(b[i]);
     x32[i] = float(x[i]);
   }
-}
-
-__global__ __launch_bounds__(kBlock) void widen_kernel(int n, const float* __restrict__ in, double* __restrict__ out) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) out[i] = double(in[i]);
 }
 
 struct FdLayout {
@@ -729,8 +762,8 @@ static gmr_status fd_solve(const gmr_csr* A64, const gmr_csr* A32, const double*
       *res = R1;
       return st1;
     }
-    widen_kernel<<<stream_grid(n), kBlock, 0, s>>>(n, x32, x);
-    GMR_TRY(check_launch("widen_kernel"));
+    cast_vec_kernel<float, double><<<stream_grid(n), kBlock, 0, s>>>(n, x32, x, nullptr);
+    GMR_TRY(check_launch("cast_vec_kernel"));
   }
   if (res32) *res32 = R1;
   gmr_params p2 = *prm;
@@ -743,6 +776,7 @@ static gmr_status fd_solve(const gmr_csr* A64, const gmr_csr* A32, const double*
   R.cycles += R1.cycles;
   R.iters += R1.iters;
   R.history_len += R1.history_len;
+  R.loss_of_accuracy += R1.loss_of_accuracy;
   R.prof_ms += R1.prof_ms;
   R.prof_launches += R1.prof_launches;
   R.prof_bytes += R1.prof_bytes;
@@ -890,7 +924,7 @@ gmr_status poly_prec_setup(const gmr_csr* A, int32_t degree, const void* v0, voi
                            size_t ws_bytes, gmr_poly** out, void* stream) {
   GMR_TRY(check_csr(A, "poly_prec_setup"));
   if (!v0 || !out) return fail(GMR_ERR_INVALID, "poly_prec_setup: null pointer");
-  if (degree < 0 || degree > 64) return fail(GMR_ERR_UNSUPPORTED, "poly_prec_setup: degree must be in [0, 64]");
+  if (degree < 0 || degree > 128) return fail(GMR_ERR_UNSUPPORTED, "poly_prec_setup: degree must be in [0, 128]");
   *out = nullptr;
   if (A->dtype == GMR_F64) return poly_setup_t<double>(A, degree, v0, ws, ws_bytes, out, (hipStream_t)stream);
   return poly_setup_t<float>(A, degree, v0, ws, ws_bytes, out, (hipStream_t)stream);
@@ -968,6 +1002,22 @@ gmr_status gmres_ir_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly
   GMR_TRY(solve_common_checks(params, b, x, result));
   SolveArgs a{A32, A64, P, b, x, params, ws, ws_bytes, result, hist, (hipStream_t)stream};
   return solve_impl<float, double>(a);
+}
+
+gmr_status gmres_f32prec_solve(const gmr_csr* A64, const gmr_csr* A32, const gmr_poly* P32, const double* b,
+                               double* x, const gmr_params* params, void* ws, size_t ws_bytes,
+                               gmr_result* result, double* hist, void* stream) {
+  GMR_TRY(check_csr(A64, "gmres_f32prec_solve(A64)"));
+  GMR_TRY(check_csr(A32, "gmres_f32prec_solve(A32)"));
+  if (A64->dtype != GMR_F64 || A32->dtype != GMR_F32)
+    return fail(GMR_ERR_INVALID, "gmres_f32prec_solve: A64 must be float64 and A32 float32");
+  if (A64->n != A32->n || A64->nnz != A32->nnz)
+    return fail(GMR_ERR_INVALID, "gmres_f32prec_solve: A64 and A32 differ in size");
+  if (!P32 || P32->dtype != GMR_F32)
+    return fail(GMR_ERR_INVALID, "gmres_f32prec_solve: needs a float32 polynomial");
+  GMR_TRY(solve_common_checks(params, b, x, result));
+  SolveArgs a{A64, A64, P32, b, x, params, ws, ws_bytes, result, hist, (hipStream_t)stream, A32};
+  return solve_impl<double, double>(a);
 }
 
 size_t gmres_fd_workspace_bytes(int32_t n, const gmr_params* params) {

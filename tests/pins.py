@@ -356,3 +356,40 @@ def check_gmres_fd():
 
 
 ALL_CHECKS.append(check_gmres_fd)
+
+
+# --- O5c float32 preconditioner inside float64 GMRES, loss of accuracy ------
+def check_f32_poly_in_f64_gmres_loses_accuracy():
+    # 3D Laplacian on 10^3, b = ones, GMRES(50), GMRES polynomial of degree 10
+    A = W.laplace3d(10)
+    b = np.ones(A.n)
+    x0 = np.zeros(A.n)
+    v0 = W.poly_start_vector(A.n, 0)
+    r64 = O.poly_roots(A, 10, v0, np.float64)
+    r32 = O.poly_roots(A, 10, v0.astype(np.float32), np.float32)
+    mixed = O.cast_wrapped(lambda v: O.poly_apply(A, r32, v, np.float32))
+    y = mixed(rng(33).standard_normal(A.n))
+    assert y.dtype == np.float64 and np.array_equal(y.astype(np.float32).astype(np.float64), y)
+    # the float32 polynomial is float32 arithmetic: it departs from the same roots
+    # applied in float64 by more than one rounding of the result
+    v = rng(34).standard_normal(A.n)
+    y32, y64 = O.poly_apply(A, r32, v, np.float32), O.poly_apply(A, r32, v, np.float64)
+    assert y32.dtype == np.float32
+    diff = np.linalg.norm(y32 - y64) / np.linalg.norm(y64)
+    assert 1e-7 < diff < 1e-4, diff
+    # float64 polynomial: one cycle, implicit and explicit residuals agree
+    d = O.gmres(A, b, x0, 50, 1e-10, 500, prec=lambda v: O.poly_apply(A, r64, v, np.float64))
+    assert d.converged and d.cycles == 1 and d.loss_of_accuracy == 0
+    # float32 polynomial: the first cycle stops on its implicit residual while the
+    # explicit one is only float32-accurate (§V-F); a restart from the explicit
+    # residual corrects it
+    mx = O.gmres(A, b, x0, 50, 1e-10, 500, prec=mixed)
+    assert mx.loss_of_accuracy >= 1 and mx.converged
+    assert 1e-9 < mx.history[1] < 1e-4, mx.history
+    assert np.linalg.norm(b - _dense(A) @ mx.x) / np.linalg.norm(b) <= 1e-10
+    st = O.gmres(A, b, x0, 50, 1e-10, 500, prec=mixed, stop_on_loss=True)
+    assert st.stopped_on_loss and not st.converged and st.cycles == 1
+    assert st.rel_res == mx.history[1]
+
+
+ALL_CHECKS.append(check_f32_poly_in_f64_gmres_loses_accuracy)

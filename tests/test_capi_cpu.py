@@ -80,7 +80,7 @@ def test_argument_errors_before_device_work():
     assert lib.cgs2_orth(0, 10, 300, 1, 10, 1, 1, None, 0, None) == -5
     assert lib.cgs2_orth(0, 10, 3, 1, 5, 1, 1, None, 0, None) == -1
     assert lib.cgs2_orth(0, 10, 3, 1, 10, 1, 1, None, 0, None) == -3
-    assert lib.poly_prec_setup(C.byref(A), 80, 1, None, 0, C.byref(C.c_void_p()), None) == -5
+    assert lib.poly_prec_setup(C.byref(A), 129, 1, None, 0, C.byref(C.c_void_p()), None) == -5
     assert lib.spmv(C.byref(A), 5, 5, None) == -1
 
 
@@ -105,6 +105,14 @@ def test_fd_host_checks_without_device():
     assert fd(A64, A32, 50, ws=256, nws=16) == -3 and b"workspace" in lib.gmr_last_error()
     assert lib.gmres_fd_solve(C.byref(A64), C.byref(A32), 8, 8, C.byref(p), 10, None, 0, C.byref(res),
                               None, None, None) == -1
+    # float32 polynomial inside float64 GMRES: a polynomial is required
+    assert lib.gmres_f32prec_solve(C.byref(A64), C.byref(A32), None, 8, 16, C.byref(p), None, 0, C.byref(res),
+                                   None, None) == -1
+    assert b"float32 polynomial" in lib.gmr_last_error()
+    assert lib.gmres_f32prec_solve(C.byref(A64), C.byref(A64), None, 8, 16, C.byref(p), None, 0, C.byref(res),
+                                   None, None) == -1
+    # the float64 workspace with a polynomial has room for the float32 copies
+    assert lib.gmres_workspace_bytes(1000, C.byref(p), 1, 1) >= lib.gmres_workspace_bytes(1000, C.byref(p), 1, 0) + 4 * 8 * 1000 + 2 * 4 * 1000
 
 
 def test_harmonic_ritz_matches_oracle():

@@ -322,9 +322,11 @@ def test_poly_f32_apply_close_to_oracle():
     P = G.poly_prec_setup(A32, 8, t32(v0))
     r = P.roots()
     assert np.all(np.abs(r.imag) == 0) and np.all(r.real > 0)
+    rref = O.poly_roots(A, 8, v0.astype(np.float32), np.float32)
+    assert np.allclose(np.sort_complex(r), np.sort_complex(rref), rtol=1e-5, atol=0)
     x = W.uniform_pm1(12, A.n)
     y = host(G.poly_prec_apply(P, A32, t32(x))).astype(np.float64)
-    yref = O.poly_apply(A, r, x, np.float64)
+    yref = O.poly_apply(A, rref, x, np.float64)
     assert np.allclose(y, yref, rtol=0, atol=2e-4 * np.abs(yref).max())
 
 
@@ -339,7 +341,7 @@ def test_gmres_ir_poly_small_convdiff():
     assert res.converged and res.iters % 20 == 0
     xh = host(x)
     assert np.linalg.norm(p.b - O.spmv(p.A, xh)) / np.linalg.norm(p.b) <= 1e-10
-    roots32 = P32.roots()
+    roots32 = O.poly_roots(p.A, 8, v0.astype(np.float32), np.float32)
     prec = lambda v: O.poly_apply(p.A, roots32, v, np.float32)
     ref = O.gmres_ir(p.A, p.b, np.zeros(p.A.n), 20, 1e-10, 20000, prec32=prec)
     say(res.cycles, ref.cycles)

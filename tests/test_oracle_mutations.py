@@ -115,6 +115,10 @@ def fd_phase1_float64(A, b, x0, m, tol, switch_iters, max_iters):
     second = K.gmres(A, b, x, m, tol, max_iters - (first.iters if first else 0), dt=np.float64)
     return first, second
 
+def poly_apply_f64_always(A, roots, x, dt=np.float64):
+    return _orig_poly_apply(A, roots, x, np.float64)  # mistake: ignores the working precision
+
+
 MUTATIONS = {
     "spmv_drop_last": ("spmv", spmv_drop_last),
     "spmv_row_index": ("spmv", spmv_row_index),
@@ -126,6 +130,7 @@ MUTATIONS = {
     "harmonic_unsquared": ("harmonic_ritz_values", harmonic_unsquared),
     "fd_phase2_from_x0": ("gmres_fd", fd_phase2_from_x0),
     "fd_phase1_float64": ("gmres_fd", fd_phase1_float64),
+    "poly_apply_f64_always": ("poly_apply", poly_apply_f64_always),
 }
 
 FAST_CHECKS = [c for c in pins.ALL_CHECKS if c.__name__ not in
