@@ -20,6 +20,8 @@ Other workloads (each prints its own line; the default line is the one above):
              float32 GMRES(50) for s iterations, then float64 GMRES(50)
   prec32     polynomial degrees 10..70 on the same Laplacian: float64 GMRES with
              a float64 or a float32 polynomial (loss of accuracy), and GMRES-IR
+  bjac       block Jacobi (block 1 and 42) on the 2500^2 convection-diffusion
+             matrix: GMRES-IR with float32 blocks vs float64 GMRES
 
 Extra fields: the float64 GMRES time on the same GPU and the ratio,
 per-kernel-family time and GB/s (the analogue of the paper's Table I), the
@@ -471,6 +473,78 @@ def prec32_sweep(args):
     }
 
 
+def bjac_leg(args):
+    """Block Jacobi (§III-D, "J k" of §V-G) on the 2500^2 convection-diffusion matrix:
+    float64 GMRES(m) with float64 blocks, float64 GMRES(m) with float32 blocks, and
+    GMRES(m)-IR with float32 blocks, for block sizes 1 and 42."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07544_amd as G
+    import workloads as W
+
+    dev = "cuda:0"
+    N = args.grid or 2500
+    m = args.restart or 50
+    log("bench: building the workload")
+    prob = W.config3_convdiff(N=N, restart=m, degree=0)
+    A64 = G.DeviceCSR.from_host(prob.A, dev)
+    A32 = A64.to_f32()
+    b = torch.from_numpy(prob.b).to(dev)
+    x = torch.zeros_like(b)
+    ws = G.alloc_workspace(G.workspace_bytes(prob.A.n, m, G.GMR_F64, True), dev)
+    Ah = host_csr(prob.A)
+    cap = 20000
+
+    def run(fn):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, r = fn()
+        sec = time.perf_counter() - t0
+        xh = x.cpu().numpy()
+        rel = float(np.linalg.norm(prob.b - Ah @ xh) / np.linalg.norm(prob.b))
+        return {"status": r.status_name, "iters": r.iters, "cycles": r.cycles, "seconds": round(sec, 4),
+                "rel_res": rel, "loss_of_accuracy": r.loss_of_accuracy}
+
+    rows = []
+    for k in [int(v) for v in args.blocks.split(",")]:
+        log(f"bench: block Jacobi {k}: setup (outside the timed solves)")
+        J64 = G.bjac_prec_setup(A64, k)
+        J32 = G.bjac_prec_setup(A32, k)
+        row = {"block": k}
+        row["f64_f64blocks"] = run(lambda: G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=cap, ws=ws, P=J64))
+        row["f64_f32blocks"] = run(lambda: G.gmres_f32prec_solve(A64, A32, J32, b, x, restart=m, tol=1e-10,
+                                                                 max_iters=cap, ws=ws))
+        row["ir_f32blocks"] = run(lambda: G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=cap,
+                                                           ws=ws, P=J32))
+        x.zero_()
+        _, pr = G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=cap, ws=ws, P=J32, prof="bjac")
+        row["bjac_apply_f32"] = {"launches": pr.prof_launches,
+                                 "avg_launch_us": round(1e3 * pr.prof_ms / max(1, pr.prof_launches), 2),
+                                 "gbs": round(pr.prof_bytes / (pr.prof_ms * 1e-3) / 1e9, 1) if pr.prof_ms else None}
+        x.zero_()
+        _, pr = G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=cap, ws=ws, P=J64, prof="bjac")
+        row["bjac_apply_f64"] = {"launches": pr.prof_launches,
+                                 "avg_launch_us": round(1e3 * pr.prof_ms / max(1, pr.prof_launches), 2),
+                                 "gbs": round(pr.prof_bytes / (pr.prof_ms * 1e-3) / 1e9, 1) if pr.prof_ms else None}
+        row["ir_speedup_vs_fp64"] = round(row["f64_f64blocks"]["seconds"] / row["ir_f32blocks"]["seconds"], 3)
+        rows.append(row)
+        log("bench: " + json.dumps(row))
+        del J64, J32
+    best = min(rows, key=lambda r: r["ir_f32blocks"]["seconds"])
+    return {
+        "metric": METRIC, "value": best["ir_f32blocks"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": round(1e3 * best["ir_f32blocks"]["seconds"], 3), "higher_is_better": False,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": (f"block Jacobi sizes {args.blocks}: GMRES({m})-IR with float32 blocks vs float64 "
+                                f"GMRES({m}) with float64 or float32 blocks; upwind convection-diffusion eps=1e-3, "
+                                f"wind (cos pi x, sin pi y) on {N}^2 (n={prob.A.n}), b=A*x_true seed 3, x0=0, tol 1e-10"),
+                   "n": prob.A.n, "nnz": prob.A.nnz, "restart": m, "tol": 1e-10},
+        "sweep": rows,
+    }
+
+
 def batch(args):
     import numpy as np
     import torch
@@ -595,7 +669,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace3d",
-                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd", "prec32"])
+                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd", "prec32", "bjac"])
     ap.add_argument("--grid", type=int, default=0, help="grid side (0: the workload's own)")
     ap.add_argument("--restart", type=int, default=0, help="restart length (0: the workload's own)")
     ap.add_argument("--train", type=int, default=192, help="predictor: training systems")
@@ -603,6 +677,7 @@ def main():
     ap.add_argument("--fd-stride", type=int, default=0, help="fd: switch-point stride (0: 5 restarts)")
     ap.add_argument("--fd-max", type=int, default=0, help="fd: last switch point (0: float64 GMRES's count)")
     ap.add_argument("--degrees", default="10,20,30,40,50,60,70", help="prec32: polynomial degrees")
+    ap.add_argument("--blocks", default="1,42", help="bjac: block sizes")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
@@ -637,6 +712,8 @@ def main():
         out = fd_sweep(args)
     elif args.workload == "prec32":
         out = prec32_sweep(args)
+    elif args.workload == "bjac":
+        out = bjac_leg(args)
     else:
         out = single_system(args, args.workload)
     print(json.dumps(out), flush=True)

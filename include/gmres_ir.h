@@ -66,7 +66,7 @@ typedef struct {
  * with HIP events and reports their summed duration and algorithmic bytes. */
 typedef enum {
   GMR_PROF_NONE = 0, GMR_PROF_SPMV = 1, GMR_PROF_CGS_DOTS = 2, GMR_PROF_CGS_UPDATE_DOTS = 3,
-  GMR_PROF_CGS_UPDATE_NORM = 4, GMR_PROF_POLY_STEP = 5, GMR_PROF_RESIDUAL = 6
+  GMR_PROF_CGS_UPDATE_NORM = 4, GMR_PROF_POLY_STEP = 5, GMR_PROF_RESIDUAL = 6, GMR_PROF_BJAC = 7
 } gmr_prof_kernel;
 
 typedef struct {
@@ -116,7 +116,11 @@ typedef struct {
   double prof_bytes;         /* summed algorithmic bytes of the profiled launches          */
 } gmr_result;
 
-typedef struct gmr_poly gmr_poly;  /* opaque, host-side: the roots of the polynomial */
+/* Opaque host-side handle of a right preconditioner M (§III-D): a GMRES
+ * polynomial (poly_prec_setup: its roots) or block Jacobi (bjac_prec_setup:
+ * a pointer to the caller's inverted blocks).  Every solver's P argument and
+ * poly_prec_apply accept either kind. */
+typedef struct gmr_poly gmr_poly;
 
 /* Workspace (bytes, device) needed by gmres_solve / gmres_ir_solve for a system of
  * order n with the given parameters and working precision `dtype` (F64: plain
@@ -152,13 +156,36 @@ gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t
 gmr_status poly_prec_setup(const gmr_csr* A, int32_t degree, const void* v0, void* ws,
                            size_t ws_bytes, gmr_poly** out, void* stream);
 
-/* y = p(A) x with the roots of P (exactly degree products with A).  A must
- * have the dtype P was built for; x, y: device, n entries, must not overlap.
- * ws as for poly_prec_setup.  Asynchronous. */
+/* y = M x: for a polynomial p(A) x with the roots of P (exactly degree
+ * products with A); for block Jacobi the block-diagonal product with the
+ * inverted blocks (A then only gives n and the dtype, and ws may be NULL).
+ * A must have the dtype P was built for; x, y: device, n entries, must not
+ * overlap.  ws as for poly_prec_setup.  Asynchronous. */
 gmr_status poly_prec_apply(const gmr_poly* P, const gmr_csr* A, const void* x, void* y, void* ws,
                            size_t ws_bytes, void* stream);
 
 void poly_prec_destroy(gmr_poly* P);
+
+/* Device bytes of the `inv` buffer of bjac_prec_setup (0 for bad arguments):
+ * 256 bytes of status, then ceil(n/block) slots of block x block values. */
+size_t bjac_prec_bytes(int32_t n, int32_t block, int32_t dtype);
+
+/* Build the block Jacobi preconditioner M = blockdiag(A)^-1 (§III-D; the
+ * "J k" preconditioner of Table III in §V-G): diagonal blocks of `block`
+ * consecutive rows (the last one takes the remaining rows), gathered from A's
+ * CSR rows (duplicate entries are summed) and inverted on the device by
+ * Gauss-Jordan elimination with partial pivoting in A's precision (float32
+ * for the float32 copy: built and applied in float32).  1 <= block <= 64.
+ * inv: caller's device memory of bjac_prec_bytes(n, block, A->dtype) bytes,
+ * 256-byte aligned, which holds the inverted blocks (column-major per block)
+ * and must outlive the handle; the library does not free it.  A singular
+ * block (a zero or non-finite pivot) gives GMR_ERR_NONFINITE and no handle.
+ * Synchronous; *out must be released with poly_prec_destroy. */
+gmr_status bjac_prec_setup(const gmr_csr* A, int32_t block, void* inv, size_t inv_bytes, gmr_poly** out,
+                           void* stream);
+
+/* Rows per diagonal block of a block Jacobi handle; 0 for a polynomial. */
+int32_t prec_block_size(const gmr_poly* P);
 
 /* The (s+1) x s Hessenberg matrix of the Arnoldi run that built P (s = degree+1),
  * column-major with leading dimension s+1, into the host array H. */

@@ -1,4 +1,4 @@
-"""Plain CPU oracle for GMRES(m), GMRES-IR and the GMRES-polynomial preconditioner.
+"""Plain CPU oracle for GMRES(m), GMRES-IR, GMRES-FD and the polynomial and block Jacobi preconditioners.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the solver library imports this
 package; only the test-suite, the smoke check and the CPU-baseline leg of the
@@ -10,4 +10,5 @@ GPU path; the two only meet through the seeded inputs of ``workloads``.
 from .krylov import (spmv, cgs2, apply_givens_column, back_substitute, gmres,  # noqa: F401
                      gmres_ir, gmres_fd, cast_wrapped, GmresOutcome, arnoldi)
 from .poly import harmonic_ritz_values, leja_order, poly_roots, poly_apply  # noqa: F401
+from .precond import bjac_apply, diagonal_block  # noqa: F401
 from .block import block_arnoldi, block_gmres_ir, cholqr2, dependent_columns, spmm, start_block  # noqa: F401,E402

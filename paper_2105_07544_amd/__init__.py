@@ -17,7 +17,7 @@ from . import _capi
 from ._capi import GMR_F32, GMR_F64, GmresError, PROF, check
 
 __all__ = ["DeviceCSR", "Poly", "SolveResult", "workspace_bytes", "alloc_workspace", "spmv",
-           "cgs2_orth", "poly_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_solve",
+           "cgs2_orth", "poly_prec_setup", "bjac_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_solve",
            "fd_workspace_bytes",
            "hessenberg_eigvals", "harmonic_ritz", "leja_order", "Batch", "GmresError", "GMR_F32", "GMR_F64", "lib"]
 
@@ -133,11 +133,18 @@ def cgs2_orth(V: torch.Tensor, k: int, w: torch.Tensor, ws: Optional[torch.Tenso
 
 
 class Poly:
-    """Handle of a GMRES polynomial built by poly_prec_setup."""
+    """Handle of a right preconditioner: a GMRES polynomial (poly_prec_setup) or
+    block Jacobi (bjac_prec_setup, which keeps its device buffer alive here)."""
 
-    def __init__(self, handle: C.c_void_p, dtype: int):
+    def __init__(self, handle: C.c_void_p, dtype: int, keep=None):
         self._h = handle
         self.dtype = dtype
+        self._keep = keep
+
+    @property
+    def block(self) -> int:
+        """Rows per diagonal block for block Jacobi, 0 for a polynomial."""
+        return int(lib().prec_block_size(self._h))
 
     @property
     def handle(self):
@@ -178,6 +185,19 @@ def poly_prec_setup(A: DeviceCSR, degree: int, v0: torch.Tensor, ws: Optional[to
     check(lib().poly_prec_setup(C.byref(st), degree, _ptr(v0), _ptr(ws), ws.numel(), C.byref(out),
                                 _stream(A.device)))
     return Poly(out, A.dtype)
+
+
+def bjac_prec_setup(A: DeviceCSR, block: int) -> Poly:
+    """Block Jacobi M = blockdiag(A)^-1 with `block` rows per diagonal block, inverted on
+    the device in A's precision."""
+    nb = lib().bjac_prec_bytes(A.n, int(block), A.dtype)
+    if nb == 0:
+        raise GmresError(-1 if block < 1 else -5, f"bjac_prec_setup: unsupported block size {block}")
+    inv = alloc_workspace(nb, A.device)
+    out = C.c_void_p()
+    st = A.struct()
+    check(lib().bjac_prec_setup(C.byref(st), int(block), _ptr(inv), inv.numel(), C.byref(out), _stream(A.device)))
+    return Poly(out, A.dtype, keep=inv)
 
 
 def poly_prec_apply(P: Poly, A: DeviceCSR, x: torch.Tensor, y: Optional[torch.Tensor] = None,

@@ -18,11 +18,11 @@ STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", 3: "GMR_LOSS_
           -2: "GMR_ERR_HIP", -3: "GMR_ERR_WORKSPACE", -4: "GMR_ERR_NONFINITE",
           -5: "GMR_ERR_UNSUPPORTED"}
 PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_norm": 4,
-        "poly_step": 5, "residual": 6}
+        "poly_step": 5, "residual": 6, "bjac": 7}
 
 # Every symbol include/gmres_ir.h declares.
 EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "poly_prec_apply",
-            "poly_prec_destroy", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
+            "poly_prec_destroy", "bjac_prec_bytes", "bjac_prec_setup", "prec_block_size", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
             "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_workspace_bytes", "gmres_fd_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
             "batch_set_tiling", "batch_set_graph", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve", "batch_gmres_solve",
@@ -89,6 +89,12 @@ def load() -> C.CDLL:
     lib.gmres_ir_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P,
                                    C.POINTER(gmr_params), P, C.c_size_t, C.POINTER(gmr_result), P, P]
     lib.gmres_ir_solve.restype = st
+    lib.bjac_prec_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    lib.bjac_prec_bytes.restype = C.c_size_t
+    lib.bjac_prec_setup.argtypes = [C.POINTER(gmr_csr), C.c_int32, P, C.c_size_t, C.POINTER(C.c_void_p), P]
+    lib.bjac_prec_setup.restype = st
+    lib.prec_block_size.argtypes = [P]
+    lib.prec_block_size.restype = C.c_int32
     lib.gmres_f32prec_solve.argtypes = [C.POINTER(gmr_csr), C.POINTER(gmr_csr), P, P, P,
                                         C.POINTER(gmr_params), P, C.c_size_t, C.POINTER(gmr_result), P, P]
     lib.gmres_f32prec_solve.restype = st

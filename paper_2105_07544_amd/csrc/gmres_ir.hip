@@ -21,6 +21,7 @@
 #include "../../include/gmres_ir.h"
 #include "host_common.hpp"
 #include "kernels.hpp"
+#include "bjac.hpp"
 
 namespace gmr {
 
@@ -331,19 +332,57 @@ static gmr_status cgs2_passes(Ctx& c, int n, int j, const T* V, int64_t ldv, T* 
 // ---------------------------------------------------------------------------
 // Polynomial object (host-side roots)
 // ---------------------------------------------------------------------------
+// Handle of a right preconditioner: a GMRES polynomial or block Jacobi.
 struct gmr_poly {
   int32_t dtype;
+  int32_t kind = 0;            // 0: GMRES polynomial, 1: block Jacobi
   std::vector<double> re, im;  // Leja-ordered roots, rounded to dtype's precision
   std::vector<double> hess;    // Hessenberg matrix of the Arnoldi run, column-major
   int32_t ldh = 0;             // its leading dimension (degree + 2)
+  int32_t n = 0;               // block Jacobi: order of A
+  int32_t block = 0;           // block Jacobi: rows per diagonal block
+  const void* inv = nullptr;   // block Jacobi: inverted blocks (caller's device memory)
 };
 
 namespace gmr {
+
+constexpr int kPrecBjac = 1;
+
+static size_t bjac_blocks_offset() { return 256; }  // the singular-block flag comes first
+
+static int bjac_grid(int n, int k) {
+  const int nblk = ceil_div(n, k);
+  if (k >= kBjacStagedMin) return nblk;  // one block per one-wave workgroup
+  return ceil_div(ceil_div(nblk, kWave / k), kBlock / kWave);
+}
+
+// Columns per LDS chunk of the staged apply: about 8 KB of the slot, even.
+template <class T>
+static int bjac_chunk(int k) {
+  const int c = (int)(8192 / ((size_t)k * sizeof(T))) & ~1;
+  return std::max(2, std::min(c, k + (k & 1)));
+}
+
+template <class T>
+static size_t bjac_staged_lds(int k) {
+  return ((size_t)bjac_chunk<T>(k) * k + kWave) * sizeof(T);
+}
 
 template <class T>
 static gmr_status poly_apply_impl(Ctx& c, const gmr_poly* P, const gmr_csr* A, const T* x, T* y,
                                   T* P0, T* P1, T* Tt, const int* done) {
   const int n = A->n;
+  if (P->kind == kPrecBjac) {
+    const int kb = P->block;
+    GMR_TRY(c.begin(GMR_PROF_BJAC));
+    if (kb >= kBjacStagedMin)
+      bjac_apply_staged_kernel<T><<<bjac_grid(n, kb), kWave, bjac_staged_lds<T>(kb), c.s>>>(
+          n, kb, bjac_chunk<T>(kb), (const T*)P->inv, x, y, done);
+    else
+      bjac_apply_kernel<T><<<bjac_grid(n, kb), kBlock, 0, c.s>>>(n, kb, (const T*)P->inv, x, y, done);
+    GMR_TRY(check_launch("bjac_apply_kernel"));
+    return c.end(GMR_PROF_BJAC, ((double)ceil_div(n, kb) * kb * kb + 2.0 * n) * sizeof(T));
+  }
   const int k = (int)P->re.size();
   const int G = spmv_grid(n);
   const int GS = stream_grid(n);
@@ -510,6 +549,8 @@ static gmr_status solve_impl(const SolveArgs& a) {
   // float32 copies of its input, the result widened back to float64
   const bool mixed = poly && a.P->dtype == GMR_F32 && sizeof(TI) == 8;
   const gmr_csr* Ap = a.Aprec ? a.Aprec : a.Ain;
+  if (poly && a.P->kind == kPrecBjac && a.P->n != n)
+    return fail(GMR_ERR_INVALID, "block Jacobi preconditioner built for another order n");
   Ws ws{(char*)a.ws, small_layout(n)};
   const Big B = big_layout(ws.S.end, n, m, sizeof(TI), sizeof(TO), poly);
   if (!a.ws || a.ws_bytes < B.end)
@@ -930,6 +971,50 @@ gmr_status poly_prec_setup(const gmr_csr* A, int32_t degree, const void* v0, voi
   return poly_setup_t<float>(A, degree, v0, ws, ws_bytes, out, (hipStream_t)stream);
 }
 
+size_t bjac_prec_bytes(int32_t n, int32_t block, int32_t dtype) {
+  if (n <= 0 || block < 1 || block > kBjacMaxBlock || (dtype != GMR_F32 && dtype != GMR_F64)) return 0;
+  return bjac_blocks_offset() + (size_t)ceil_div(n, block) * block * block * dsize(dtype);
+}
+
+gmr_status bjac_prec_setup(const gmr_csr* A, int32_t block, void* inv, size_t inv_bytes, gmr_poly** out,
+                           void* stream) {
+  GMR_TRY(check_csr(A, "bjac_prec_setup"));
+  if (!out) return fail(GMR_ERR_INVALID, "bjac_prec_setup: null pointer");
+  if (block < 1) return fail(GMR_ERR_INVALID, "bjac_prec_setup: block < 1");
+  if (block > kBjacMaxBlock) return fail(GMR_ERR_UNSUPPORTED, "bjac_prec_setup: block > 64 is not supported");
+  const size_t need = bjac_prec_bytes(A->n, block, A->dtype);
+  if (!inv || inv_bytes < need)
+    return fail(GMR_ERR_WORKSPACE, "bjac_prec_setup: inv needs " + std::to_string(need) + " bytes");
+  if ((uintptr_t)inv % 256 != 0) return fail(GMR_ERR_INVALID, "bjac_prec_setup: inv must be 256-byte aligned");
+  *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  int* flag = (int*)inv;
+  char* blocks = (char*)inv + bjac_blocks_offset();
+  GMR_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  const int nblk = ceil_div(A->n, block);
+  if (A->dtype == GMR_F64)
+    bjac_invert_kernel<double><<<nblk, kBlock, 0, s>>>(A->n, block, A->row_ptr, A->col_idx,
+                                                      (const double*)A->val, (double*)blocks, flag);
+  else
+    bjac_invert_kernel<float><<<nblk, kBlock, 0, s>>>(A->n, block, A->row_ptr, A->col_idx,
+                                                     (const float*)A->val, (float*)blocks, flag);
+  GMR_TRY(check_launch("bjac_invert_kernel"));
+  int bad = 0;
+  GMR_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  GMR_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(GMR_ERR_NONFINITE, "bjac_prec_setup: a diagonal block is singular");
+  gmr_poly* P = new gmr_poly;
+  P->dtype = A->dtype;
+  P->kind = kPrecBjac;
+  P->n = A->n;
+  P->block = block;
+  P->inv = blocks;
+  *out = P;
+  return GMR_OK;
+}
+
+int32_t prec_block_size(const gmr_poly* P) { return P && P->kind == kPrecBjac ? P->block : 0; }
+
 gmr_status poly_prec_apply(const gmr_poly* P, const gmr_csr* A, const void* x, void* y, void* wsp,
                            size_t ws_bytes, void* stream) {
   if (!P) return fail(GMR_ERR_INVALID, "poly_prec_apply: null polynomial");
@@ -937,6 +1022,13 @@ gmr_status poly_prec_apply(const gmr_poly* P, const gmr_csr* A, const void* x, v
   if (A->dtype != P->dtype) return fail(GMR_ERR_INVALID, "poly_prec_apply: dtype of A and P differ");
   if (!x || !y || x == y) return fail(GMR_ERR_INVALID, "poly_prec_apply: bad vectors");
   const int n = A->n;
+  if (P->kind == kPrecBjac) {
+    if (P->n != n) return fail(GMR_ERR_INVALID, "poly_prec_apply: block Jacobi built for another order n");
+    Ctx c{(hipStream_t)stream, nullptr};
+    if (A->dtype == GMR_F64)
+      return poly_apply_impl<double>(c, P, A, (const double*)x, (double*)y, nullptr, nullptr, nullptr, nullptr);
+    return poly_apply_impl<float>(c, P, A, (const float*)x, (float*)y, nullptr, nullptr, nullptr, nullptr);
+  }
   const Small S = small_layout(n);
   const size_t s = dsize(A->dtype);
   const size_t need = S.end + 3 * align_up((size_t)n * s, 256);

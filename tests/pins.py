@@ -393,3 +393,36 @@ def check_f32_poly_in_f64_gmres_loses_accuracy():
 
 
 ALL_CHECKS.append(check_f32_poly_in_f64_gmres_loses_accuracy)
+
+
+# --- O6b block Jacobi ----------------------------------------------------------
+def check_bjac():
+    n = 50
+    A, D = random_csr(n, 0.15, 35, diag_shift=6.0)
+    v = rng(36).standard_normal(n)
+    # block 1 is point Jacobi: z = v / diag(A)
+    z1 = O.bjac_apply(A, 1, v)
+    assert np.allclose(z1, v / np.diag(D), rtol=1e-15, atol=0)
+    # block n is the exact inverse
+    zn = O.bjac_apply(A, n, v)
+    assert np.linalg.norm(D @ zn - v) <= 1e-13 * np.linalg.norm(v)
+    for k in (3, 7, 16):
+        # z solves blockdiag(A) z = v, with a ragged last block
+        mask = np.zeros((n, n), bool)
+        for r0 in range(0, n, k):
+            mask[r0:r0 + k, r0:r0 + k] = True
+        z = O.bjac_apply(A, k, v)
+        assert np.linalg.norm((D * mask) @ z - v) <= 1e-13 * np.linalg.norm(v), k
+        # on a matrix that is itself block diagonal, M = A^-1 and GMRES needs one iteration
+        Ab = dense_csr(D * mask)
+        out = O.gmres(Ab, v, np.zeros(n), 10, 1e-12, 10, prec=lambda w, Ab=Ab, k=k: O.bjac_apply(Ab, k, w))
+        assert out.converged and out.iters == 1, (k, out.iters)
+    # float32: a float32 factorisation, close to the float64 one
+    z32 = O.bjac_apply(A, 7, v, np.float32)
+    z64 = O.bjac_apply(A, 7, v)
+    assert z32.dtype == np.float32
+    d = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    assert 0 < d < 1e-5, d
+
+
+ALL_CHECKS.append(check_bjac)

@@ -115,6 +115,22 @@ def test_fd_host_checks_without_device():
     assert lib.gmres_workspace_bytes(1000, C.byref(p), 1, 1) >= lib.gmres_workspace_bytes(1000, C.byref(p), 1, 0) + 4 * 8 * 1000 + 2 * 4 * 1000
 
 
+def test_bjac_host_checks_without_device():
+    lib = G.lib()
+    assert lib.bjac_prec_bytes(1001, 42, 0) == 256 + 24 * 42 * 42 * 4
+    assert lib.bjac_prec_bytes(1001, 42, 1) == 256 + 24 * 42 * 42 * 8
+    assert lib.bjac_prec_bytes(10, 1, 1) == 256 + 10 * 8
+    assert lib.bjac_prec_bytes(10, 0, 1) == 0 and lib.bjac_prec_bytes(10, 65, 1) == 0
+    A = _capi.gmr_csr(10, 28, 16, 32, 48, 1)
+    out = C.c_void_p()
+    assert lib.bjac_prec_setup(C.byref(A), 0, 256, 1 << 20, C.byref(out), None) == -1
+    assert lib.bjac_prec_setup(C.byref(A), 65, 256, 1 << 20, C.byref(out), None) == -5
+    assert lib.bjac_prec_setup(C.byref(A), 4, 256, 16, C.byref(out), None) == -3
+    assert lib.bjac_prec_setup(C.byref(A), 4, 264, 1 << 20, C.byref(out), None) == -1
+    assert b"aligned" in lib.gmr_last_error()
+    assert lib.prec_block_size(None) == 0
+
+
 def test_harmonic_ritz_matches_oracle():
     import workloads as W
     for A, d in ((W.convdiff2d(30, 0.05, W.configs.uniflow_wind), 10), (W.laplace2d(12), 7)):

@@ -1,0 +1,141 @@
+"""GPU parity of the block Jacobi preconditioner: the inverted blocks, the apply,
+and the solvers that use it (float64 GMRES, GMRES-IR, float32 blocks in float64 GMRES)."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+G = pytest.importorskip("paper_2105_07544_amd")
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tdev(x, dt):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_res(A, b, x):
+    M = sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+    return float(np.linalg.norm(b - M @ x) / np.linalg.norm(b))
+
+
+def random_dominant(n, seed, per_row=7):
+    """Nonsymmetric sparse matrix with a dominant diagonal and some duplicate entries."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for r in range(n):
+        c = rng.integers(max(0, r - 40), min(n, r + 41), size=per_row)
+        rows += [r] * (per_row + 1)
+        cols += list(c) + [r]
+        vals += list(rng.standard_normal(per_row)) + [per_row + 2.0]
+    M = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()   # sums duplicates
+    M.sort_indices()
+    return W.CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("block", [1, 2, 3, 7, 8, 16, 42, 63, 64])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bjac_apply_against_oracle(block, prec):
+    say("bjac apply", prec, "block", block)
+    A = random_dominant(1001, 7 + block)   # 1001 rows: a ragged last block for every size but 1
+    dt = np.float64 if prec == "f64" else np.float32
+    Ad = G.DeviceCSR.from_host(A, DEV)
+    if prec == "f32":
+        Ad = Ad.to_f32()
+    P = G.bjac_prec_setup(Ad, block)
+    assert P.block == block and P.degree == -1
+    v = W.uniform_pm1(50 + block, A.n)
+    y = host(G.poly_prec_apply(P, Ad, tdev(v, dt))).astype(np.float64)
+    ref = O.bjac_apply(A, block, v, dt).astype(np.float64)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    say("max rel err", err)
+    assert err <= (1e-12 if prec == "f64" else 2e-5)
+
+
+def test_bjac_singular_block_is_an_error():
+    # an empty row makes its diagonal block singular
+    n = 100
+    rp = np.arange(n + 1, dtype=np.int32)
+    rp[51:] -= 1            # row 50 is empty
+    ci = np.array([r for r in range(n) if r != 50], np.int32)
+    A = W.CSR(n, rp, ci, np.full(n - 1, 2.0))
+    Ad = G.DeviceCSR.from_host(A, DEV)
+    with pytest.raises(G.GmresError) as e:
+        G.bjac_prec_setup(Ad, 8)
+    assert e.value.status == -4
+    # the other blocks are regular: a block size that isolates row 50 fails the same way
+    with pytest.raises(G.GmresError):
+        G.bjac_prec_setup(Ad, 1)
+    P = G.bjac_prec_setup(G.DeviceCSR.from_host(random_dominant(100, 3), DEV), 8)
+    assert P.block == 8
+
+
+def test_bjac_block_size_limits():
+    Ad = G.DeviceCSR.from_host(random_dominant(200, 4), DEV)
+    for bad, code in ((0, -1), (65, -5)):
+        with pytest.raises(G.GmresError) as e:
+            G.bjac_prec_setup(Ad, bad)
+        assert e.value.status == code
+    # a handle built for another order is refused by the solver
+    P = G.bjac_prec_setup(G.DeviceCSR.from_host(random_dominant(150, 5), DEV), 4)
+    with pytest.raises(G.GmresError):
+        G.gmres_solve(Ad, tdev(np.ones(200), np.float64), P=P)
+
+
+def test_solvers_with_bjac_against_oracle():
+    say("solvers with block Jacobi 42, convdiff 60^2")
+    p = W.config3_convdiff(N=60, restart=20, degree=0)
+    A64 = G.DeviceCSR.from_host(p.A, DEV)
+    A32 = A64.to_f32()
+    b = tdev(p.b, np.float64)
+    J64 = G.bjac_prec_setup(A64, 42)
+    J32 = G.bjac_prec_setup(A32, 42)
+    x1, r1 = G.gmres_solve(A64, b, restart=20, tol=1e-10, max_iters=20000, P=J64)
+    x2, r2 = G.gmres_ir_solve(A64, A32, b, restart=20, tol=1e-10, max_iters=20000, P=J32)
+    x3, r3 = G.gmres_f32prec_solve(A64, A32, J32, b, restart=20, tol=1e-10, max_iters=20000)
+    x0, r0 = G.gmres_solve(A64, b, restart=20, tol=1e-10, max_iters=20000)
+    ref64 = O.gmres(p.A, p.b, np.zeros(p.A.n), 20, 1e-10, 20000, prec=lambda v: O.bjac_apply(p.A, 42, v))
+    ref_ir = O.gmres_ir(p.A, p.b, np.zeros(p.A.n), 20, 1e-10, 20000,
+                        prec32=lambda v: O.bjac_apply(p.A, 42, v, np.float32))
+    say("iters: f64", r1.iters, "oracle", ref64.iters, "| IR", r2.iters, "oracle", ref_ir.iters,
+        "| f64+f32 blocks", r3.iters, r3.loss_of_accuracy, "| none", r0.iters)
+    for x, r in ((x1, r1), (x2, r2), (x3, r3)):
+        assert r.converged and rel_res(p.A, p.b, host(x)) <= 1e-10
+    assert abs(r1.iters - ref64.iters) <= max(2, 0.05 * ref64.iters)
+    assert abs(r2.cycles - ref_ir.cycles) <= max(1, 0.1 * ref_ir.cycles)
+    assert r1.iters < r0.iters   # the preconditioner helps on this problem
+
+
+def test_bjac_full_size_sampled_blocks():
+    """Block Jacobi 42 on the 2500^2 convection-diffusion matrix (n = 6.25M): sampled
+    blocks of one float32 apply against the oracle's per-block solves."""
+    say("bjac 42 full-size convdiff, sampled blocks")
+    p = W.config3_convdiff()
+    A32 = G.DeviceCSR.from_host(p.A, DEV).to_f32()
+    J = G.bjac_prec_setup(A32, 42)
+    v = W.uniform_pm1(77, p.A.n)
+    y = host(G.poly_prec_apply(J, A32, tdev(v, np.float32))).astype(np.float64)
+    nblk = -(-p.A.n // 42)
+    rng = np.random.default_rng(78)
+    for b in list(rng.choice(nblk - 1, 24, replace=False)) + [nblk - 1]:
+        r0, r1 = 42 * int(b), min(42 * int(b) + 42, p.A.n)
+        B = O.diagonal_block(p.A, r0, r1).astype(np.float32)
+        ref = np.linalg.solve(B, v[r0:r1].astype(np.float32)).astype(np.float64)
+        assert np.abs(y[r0:r1] - ref).max() <= 2e-5 * np.abs(ref).max(), b

@@ -5,10 +5,11 @@ import pytest
 import oracle
 import oracle.krylov as K
 import oracle.poly as P
+import oracle.precond as O_pre
 import pins
 
 
-def _patch(monkeypatch, name, fn, modules=(oracle, K, P)):
+def _patch(monkeypatch, name, fn, modules=(oracle, K, P, O_pre)):
     for m in modules:
         if hasattr(m, name):
             monkeypatch.setattr(m, name, fn)
@@ -119,6 +120,26 @@ def poly_apply_f64_always(A, roots, x, dt=np.float64):
     return _orig_poly_apply(A, roots, x, np.float64)  # mistake: ignores the working precision
 
 
+def bjac_transposed(A, block, v, dt=np.float64):
+    dt = np.dtype(dt)
+    v = np.asarray(v).astype(dt)
+    z = np.zeros(A.n, dtype=dt)
+    for r0 in range(0, A.n, block):
+        r1 = min(r0 + block, A.n)
+        z[r0:r1] = np.linalg.solve(O_pre.diagonal_block(A, r0, r1).astype(dt).T, v[r0:r1])  # mistake
+    return z
+
+
+def bjac_short_blocks(A, block, v, dt=np.float64):
+    dt = np.dtype(dt)
+    v = np.asarray(v).astype(dt)
+    z = np.zeros(A.n, dtype=dt)
+    for r0 in range(0, A.n, block):
+        r1 = min(r0 + block - 1, A.n)   # mistake: drops the last row of every block
+        z[r0:r1] = np.linalg.solve(O_pre.diagonal_block(A, r0, r1).astype(dt), v[r0:r1])
+    return z
+
+
 MUTATIONS = {
     "spmv_drop_last": ("spmv", spmv_drop_last),
     "spmv_row_index": ("spmv", spmv_row_index),
@@ -131,6 +152,8 @@ MUTATIONS = {
     "fd_phase2_from_x0": ("gmres_fd", fd_phase2_from_x0),
     "fd_phase1_float64": ("gmres_fd", fd_phase1_float64),
     "poly_apply_f64_always": ("poly_apply", poly_apply_f64_always),
+    "bjac_transposed": ("bjac_apply", bjac_transposed),
+    "bjac_short_blocks": ("bjac_apply", bjac_short_blocks),
 }
 
 FAST_CHECKS = [c for c in pins.ALL_CHECKS if c.__name__ not in
