@@ -259,6 +259,28 @@ def single_system(args, kind):
     t_64 = (time.perf_counter() - t0) / len(r64)
     assert all(r.converged for r in r64), [r.status_name for r in r64]
 
+    half = None
+    if not degree and prob.A.n > 1024:
+        # the third precision (float16 basis), reported beside the paper's method
+        log("bench: GMRES-IR with the float16 basis")
+        x.zero_()
+        G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir, half_basis=True)
+        t0 = time.perf_counter()
+        rh = [G.gmres_ir_solve(A64, A32, b, x.zero_(), restart=m, tol=1e-10, max_iters=200000, ws=ws_ir,
+                               half_basis=True)[1] for _ in range(max(1, min(args.steps, 3)))]
+        t_h = (time.perf_counter() - t0) / len(rh)
+        xh16 = x.cpu().numpy()
+        rel16 = float(np.linalg.norm(prob.b - host_csr(prob.A) @ xh16) / np.linalg.norm(prob.b))
+        half = {"seconds": round(t_h, 5), "iters": rh[-1].iters, "cycles": rh[-1].cycles, "rel_res": rel16,
+                "speedup_vs_fp64": round(t_64 / t_h, 3), "speedup_vs_f32_basis": round(t_ir / t_h, 3)}
+        assert all(r.converged for r in rh) and rel16 <= 1e-10, half
+        if not args.no_breakdown:
+            for fam in ("spmv", "cgs_dots", "cgs_update_dots", "cgs_update_norm"):
+                x.zero_()
+                rp = G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir,
+                                      half_basis=True, prof=fam)[1]
+                half[fam + "_gbs"] = round(rp.prof_bytes / (rp.prof_ms * 1e-3) / 1e9, 1) if rp.prof_ms else None
+                half[fam + "_ms"] = round(rp.prof_ms, 3)
     mixed = None
     if degree:
         # the middle option of §V-C: float64 GMRES with the float32 polynomial
@@ -294,6 +316,7 @@ def single_system(args, kind):
         "ms_per_step_unprofiled": round(1e3 * float(np.median(unprof)), 3) if unprof else None,
         "graph": graph, "persistent_cycle": pers,
         **({"fp64_gmres_f32poly": mixed} if mixed else {}),
+        **({"ir_half_basis": half} if half else {}),
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": stored_traffic(dominant, kind), "launches": prof_launches,

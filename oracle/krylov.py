@@ -223,8 +223,12 @@ def gmres(A, b, x0, m: int, tol: float, max_iters: int, dt=np.float64,
 # and gamma scales the correction back.
 # ---------------------------------------------------------------------------
 def gmres_ir(A, b, x0, m: int, tol: float, max_iters: int,
-             prec32: Optional[Callable] = None, max_cycles: Optional[int] = None) -> GmresOutcome:
+             prec32: Optional[Callable] = None, max_cycles: Optional[int] = None,
+             half_basis: bool = False) -> GmresOutcome:
     n = A.n
+    # third precision (§VI): the basis used by Gram-Schmidt and the update is
+    # stored in float16; the SpMV takes the float32 vector before rounding
+    store = (lambda v: half_store(v, half_sigma(n))) if half_basis else (lambda v: v)
     b = np.asarray(b, dtype=np.float64)
     bnorm = float(np.linalg.norm(b))
     f32 = np.float32
@@ -241,11 +245,12 @@ def gmres_ir(A, b, x0, m: int, tol: float, max_iters: int,
         V = np.zeros((n, m + 1), dtype=f32)
         H = np.zeros((m + 1, m))
         cs, sn, g = np.zeros(m), np.zeros(m), np.zeros(m + 1)
-        V[:, 0] = v / beta0
+        vj = v / beta0
+        V[:, 0] = store(vj)
         g[0] = float(beta0)
         k = 0
         for j in range(m):
-            z = prec32(V[:, j]) if prec32 else V[:, j]
+            z = prec32(V[:, j]) if prec32 else vj
             w = spmv(A, z, f32)
             w, h1, h2, beta = cgs2(V, j + 1, w)
             H[: j + 1, j] = h1.astype(np.float64) + h2.astype(np.float64)
@@ -256,7 +261,8 @@ def gmres_ir(A, b, x0, m: int, tol: float, max_iters: int,
             out.implicit_history.append(gamma * res / bnorm)
             brk = _is_breakdown(beta, f32)
             if not brk:
-                V[:, j + 1] = w / beta
+                vj = w / beta
+                V[:, j + 1] = store(vj)
             if brk or it >= max_iters:
                 break
         y = back_substitute(H[:k, :k], g[:k])
@@ -303,3 +309,19 @@ def gmres_fd(A, b, x0, m: int, tol: float, switch_iters: int, max_iters: int):
 # ---------------------------------------------------------------------------
 def cast_wrapped(prec32: Callable) -> Callable:
     return lambda v: np.asarray(prec32(np.asarray(v).astype(np.float32)), dtype=np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# O5d: float16 storage of a float32 basis vector (the third precision of
+# §VI): entries of a unit vector are about 1/sqrt(n), below float16's normal
+# range for large n, so the vector is scaled by a power of two sigma ~ sqrt(n)
+# before rounding (round to nearest even) and unscaled after; both scalings
+# are exact.
+# ---------------------------------------------------------------------------
+def half_sigma(n: int) -> float:
+    return float(2.0 ** min(15, max(0, int(round(0.5 * np.log2(n))))))
+
+
+def half_store(v: np.ndarray, sigma: float) -> np.ndarray:
+    f32 = np.float32
+    return ((np.asarray(v, dtype=f32) * f32(sigma)).astype(np.float16).astype(f32)) / f32(sigma)

@@ -233,9 +233,10 @@ class SolveResult:
 
 
 def _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph=False, persistent=False,
-            stop_on_loss=False):
+            stop_on_loss=False, half_basis=False):
     flags = ((_capi.GMR_FLAG_GRAPH if graph else 0) | (_capi.GMR_FLAG_PERSISTENT if persistent else 0)
-             | (_capi.GMR_FLAG_STOP_ON_LOSS if stop_on_loss else 0))
+             | (_capi.GMR_FLAG_STOP_ON_LOSS if stop_on_loss else 0)
+             | (_capi.GMR_FLAG_HALF_BASIS if half_basis else 0))
     return _capi.gmr_params(int(restart), float(tol), int(max_iters), int(max_cycles),
                             int(stagnation_cycles), PROF[prof] if isinstance(prof, str) else int(prof), flags)
 
@@ -250,13 +251,15 @@ def _result(res: _capi.gmr_result, hist: np.ndarray) -> SolveResult:
 def gmres_solve(A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None, *, restart: int = 50,
                 tol: float = 1e-10, max_iters: int = 100000, max_cycles: int = 0,
                 P: Optional[Poly] = None, ws: Optional[torch.Tensor] = None, prof="none",
-                graph: bool = False, persistent: bool = False, stop_on_loss: bool = False):
+                graph: bool = False, persistent: bool = False, stop_on_loss: bool = False,
+                half_basis: bool = False):
     """Restarted GMRES(m) in A's precision.  x (x0, updated in place) defaults to 0.
     persistent: one single-block kernel per restart cycle for small systems.
-    stop_on_loss: end at the first loss of accuracy instead of restarting."""
+    stop_on_loss: end at the first loss of accuracy instead of restarting.
+    half_basis: passed through as GMR_FLAG_HALF_BASIS (only GMRES-IR supports it)."""
     if x is None:
         x = torch.zeros_like(b)
-    prm = _params(restart, tol, max_iters, max_cycles, 0, prof, graph, persistent, stop_on_loss)
+    prm = _params(restart, tol, max_iters, max_cycles, 0, prof, graph, persistent, stop_on_loss, half_basis)
     if ws is None:
         ws = alloc_workspace(workspace_bytes(A.n, restart, A.dtype, P is not None), A.device)
     cap = max_cycles + 1 if max_cycles > 0 else 4096
@@ -274,12 +277,14 @@ def gmres_ir_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, x: Optional[
                    restart: int = 50, tol: float = 1e-10, max_iters: int = 100000, max_cycles: int = 0,
                    stagnation_cycles: int = 0, P: Optional[Poly] = None,
                    ws: Optional[torch.Tensor] = None, prof="none", graph: bool = False,
-                   persistent: bool = False):
+                   persistent: bool = False, half_basis: bool = False):
     """GMRES-IR: float32 inner GMRES(m) on A32, float64 residual and update on A64.
-    persistent: one single-block kernel per restart cycle for small systems."""
+    persistent: one single-block kernel per restart cycle for small systems.
+    half_basis: store the inner Krylov basis in float16 (no preconditioner)."""
     if x is None:
         x = torch.zeros_like(b)
-    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph, persistent)
+    prm = _params(restart, tol, max_iters, max_cycles, stagnation_cycles, prof, graph, persistent,
+                  half_basis=half_basis)
     if ws is None:
         ws = alloc_workspace(workspace_bytes(A64.n, restart, GMR_F32, P is not None), A64.device)
     cap = max_cycles + 1 if max_cycles > 0 else 4096

@@ -14,6 +14,7 @@ GMR_F32, GMR_F64 = 0, 1
 GMR_FLAG_GRAPH = 1
 GMR_FLAG_PERSISTENT = 2
 GMR_FLAG_STOP_ON_LOSS = 4
+GMR_FLAG_HALF_BASIS = 8
 STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", 3: "GMR_LOSS_OF_ACCURACY", -1: "GMR_ERR_INVALID",
           -2: "GMR_ERR_HIP", -3: "GMR_ERR_WORKSPACE", -4: "GMR_ERR_NONFINITE",
           -5: "GMR_ERR_UNSUPPORTED"}

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmresir.so")
 SOURCES = ["gmres_ir.hip", "batched.hip", "predictor.hip", "hessenberg.cpp"]
-HEADERS = ["device_common.hpp", "kernels.hpp", "host_common.hpp", "bjac.hpp"]
+HEADERS = ["device_common.hpp", "kernels.hpp", "host_common.hpp", "bjac.hpp", "half_basis.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

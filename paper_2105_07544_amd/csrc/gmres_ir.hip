@@ -22,6 +22,7 @@
 #include "host_common.hpp"
 #include "kernels.hpp"
 #include "bjac.hpp"
+#include "half_basis.hpp"
 
 namespace gmr {
 
@@ -327,6 +328,64 @@ static gmr_status cgs2_passes(Ctx& c, int n, int j, const T* V, int64_t ldv, T* 
   return launch_update_norm<T, MODE>(c, n, j, V, ldv, ws.h2t<T>(), w, ws, cs, last_jc, hout, done);
 }
 
+// The three CGS2 passes with the basis stored in float16 (scaled by sigma).
+static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t ldv, float* w, const Ws& ws,
+                                 CycleState cs, int last_jc, float inv_sigma, const int* done) {
+  double* part = ws.partial();
+  const double vb = (double)j * n * sizeof(half_t);
+  // pass 1: h1 = V^T w
+  GMR_TRY(c.begin(GMR_PROF_CGS_DOTS));
+  const int G = dots_grid(ceil_div(n, 2));
+#define GMR_HD(K, NQ) hb_dots_kernel<K, NQ><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, inv_sigma, part, done)
+  if (j <= 8) GMR_HD(8, 1);
+  else if (j <= 16) GMR_HD(16, 1);
+  else if (j <= 32) GMR_HD(32, 1);
+  else if (j <= 64) GMR_HD(64, 1);
+  else GMR_HD(64, 4);
+  GMR_TRY(check_launch("hb_dots_kernel"));
+  GMR_TRY(c.end(GMR_PROF_CGS_DOTS, vb + 4.0 * n));
+  finish_cols_kernel<float><<<j, kBlock, 0, c.s>>>(G, part, cs.h1d, ws.h1t<float>(), done);
+  GMR_TRY(check_launch("finish_cols_kernel"));
+  // pass-1 update and pass-2 dots
+  GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
+  if (j > 64) {
+    hb_update_kernel<false><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w,
+                                                               part, done);
+    GMR_TRY(check_launch("hb_update_kernel"));
+    GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, vb + 8.0 * n));
+    GMR_HD(64, 4);
+    GMR_TRY(check_launch("hb_dots_kernel"));
+  } else {
+#define GMR_HUD(K) \
+  hb_update_dots_kernel<K><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w, part, done)
+    if (j <= 8) GMR_HUD(8);
+    else if (j <= 16) GMR_HUD(16);
+    else if (j <= 32) GMR_HUD(32);
+    else GMR_HUD(64);
+#undef GMR_HUD
+    GMR_TRY(check_launch("hb_update_dots_kernel"));
+    GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, vb + 8.0 * n));
+  }
+#undef GMR_HD
+  finish_cols_kernel<float><<<j, kBlock, 0, c.s>>>(G, part, cs.h2d, ws.h2t<float>(), done);
+  GMR_TRY(check_launch("finish_cols_kernel"));
+  // pass-2 update, norm, Givens
+  GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_NORM));
+  const int GS = stream_grid(n);
+  hb_update_kernel<true><<<GS, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h2t<float>(), inv_sigma, w, part, done);
+  GMR_TRY(check_launch("hb_update_kernel"));
+  GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_NORM, vb + 8.0 * n));
+  finish_norm_kernel<float, kTailGivens><<<1, kBlock, 0, c.s>>>(GS, part, cs, j, last_jc, 1e3 * 1.1754943508222875e-38,
+                                                               nullptr, done);
+  return check_launch("finish_norm_kernel");
+}
+
+// sigma = 2^round(log2 sqrt(n)), at most 2^15: the scale of the float16 basis.
+static float hb_sigma(int n) {
+  const int e = std::min(15, std::max(0, (int)std::lround(0.5 * std::log2((double)n))));
+  return std::ldexp(1.0f, e);
+}
+
 }  // namespace gmr
 
 // ---------------------------------------------------------------------------
@@ -549,6 +608,9 @@ static gmr_status solve_impl(const SolveArgs& a) {
   // float32 copies of its input, the result widened back to float64
   const bool mixed = poly && a.P->dtype == GMR_F32 && sizeof(TI) == 8;
   const gmr_csr* Ap = a.Aprec ? a.Aprec : a.Ain;
+  const bool half = (prm.flags & GMR_FLAG_HALF_BASIS) != 0;
+  if (half && (poly || sizeof(TI) != 4 || sizeof(TO) != 8))
+    return fail(GMR_ERR_UNSUPPORTED, "GMR_FLAG_HALF_BASIS needs GMRES-IR without a preconditioner");
   if (poly && a.P->kind == kPrecBjac && a.P->n != n)
     return fail(GMR_ERR_INVALID, "block Jacobi preconditioner built for another order n");
   Ws ws{(char*)a.ws, small_layout(n)};
@@ -568,8 +630,9 @@ static gmr_status solve_impl(const SolveArgs& a) {
   // one block per cycle for a small system without a polynomial (profiling
   // and graph replay keep the multi-kernel cycle)
   const bool persistent = (prm.flags & GMR_FLAG_PERSISTENT) && n <= kSmallMaxN && !poly && !graph.use &&
-                          prm.prof_kernel == GMR_PROF_NONE;
+                          !half && prm.prof_kernel == GMR_PROF_NONE;
   const double brk_thresh = sizeof(TI) == 4 ? 1e3 * 1.1754943508222875e-38 : 0.0;
+  const float sigma = hb_sigma(n);
   Prof& pf = prof_state();
   pf.family = prm.prof_kernel;
   pf.used = 0;
@@ -658,6 +721,19 @@ static gmr_status solve_impl(const SolveArgs& a) {
         GMR_TRY(check_launch("scale_kernel"));
         GMR_TRY(apply_prec(vj, Z, done));
         GMR_TRY(launch_spmv<TI>(c, a.Ain, Z, nullptr, nullptr, wn, done));
+      } else if (half) {
+        if constexpr (sizeof(TI) == 4 && sizeof(TO) == 8) {
+          half_t* Vh = reinterpret_cast<half_t*>(V);
+          GMR_TRY(c.begin(GMR_PROF_SPMV));
+          spmv_hb_kernel<<<spmv_grid(n), kBlock, 0, c.s>>>(n, a.Ain->row_ptr, a.Ain->col_idx,
+                                                          (const float*)a.Ain->val, W[cur], cs.inv_beta, sigma,
+                                                          Vh + (size_t)j * B.ldv, wn, done);
+          GMR_TRY(check_launch("spmv_hb_kernel"));
+          GMR_TRY(c.end(GMR_PROF_SPMV, spmv_bytes<float>(a.Ain) + 2.0 * n));
+          GMR_TRY(hb_cgs2_passes(c, n, j + 1, Vh, B.ldv, wn, ws, cs, mc - 1, 1.0f / sigma, done));
+        }
+        cur ^= 1;
+        continue;
       } else {
         GMR_TRY(launch_spmv<TI>(c, a.Ain, W[cur], cs.inv_beta, vj, wn, done));
       }
@@ -671,6 +747,12 @@ static gmr_status solve_impl(const SolveArgs& a) {
       GMR_TRY(apply_prec(U, Z, nullptr));
       axpy_gamma_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, Z, st_dev, x);
       GMR_TRY(check_launch("axpy_gamma_kernel"));
+    } else if (half) {
+      if constexpr (sizeof(TI) == 4 && sizeof(TO) == 8) {
+        hb_solution_update_kernel<<<stream_grid(n), kBlock, 0, c.s>>>(n, reinterpret_cast<const half_t*>(V), B.ldv,
+                                                                     cs.y, 1.0f / sigma, st_dev, x);
+        GMR_TRY(check_launch("hb_solution_update_kernel"));
+      }
     } else {
       solution_update_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, V, B.ldv, cs.y, st_dev, nullptr, x);
       GMR_TRY(check_launch("solution_update_kernel"));

@@ -426,3 +426,28 @@ def check_bjac():
 
 
 ALL_CHECKS.append(check_bjac)
+
+
+# --- O5d float16 basis ----------------------------------------------------------
+def check_half_basis():
+    assert O.half_sigma(3_375_000) == 2048.0 and O.half_sigma(1) == 1.0 and O.half_sigma(2 ** 40) == 2.0 ** 15
+    # storage: round to nearest float16 after the power-of-two scaling, so entries far
+    # below float16's normal range (1/sqrt(n) at n = 2^24) keep 11 significant bits
+    sig = O.half_sigma(2 ** 24)
+    v = (rng(37).uniform(0.5, 1.0, 1000) * np.logspace(-7, -1, 1000)).astype(np.float32)
+    st = O.half_store(v, sig)
+    assert np.array_equal((st * np.float32(sig)).astype(np.float16).astype(np.float32), st * np.float32(sig))
+    assert np.max(np.abs(st - v) / v) <= 2.0 ** -11
+    # GMRES-IR with the float16 basis: a cycle is only about float16-accurate,
+    # the float64 outer loop still reaches 1e-10
+    A = W.laplace3d(12)
+    xt = W.uniform_pm1(2, A.n)
+    b = W.host_matvec(A, xt)
+    h32 = O.gmres_ir(A, b, np.zeros(A.n), 20, 1e-10, 2000)
+    h16 = O.gmres_ir(A, b, np.zeros(A.n), 20, 1e-10, 2000, half_basis=True)
+    assert h16.converged and h32.converged
+    assert 2 * h32.history[1] < h16.history[1] < 1e-2, (h32.history[1], h16.history[1])
+    assert np.linalg.norm(b - W.host_matvec(A, h16.x)) / np.linalg.norm(b) <= 1e-10
+
+
+ALL_CHECKS.append(check_half_basis)

@@ -140,6 +140,14 @@ def bjac_short_blocks(A, block, v, dt=np.float64):
     return z
 
 
+def half_store_unscaled(v, sigma):
+    return np.asarray(v, dtype=np.float32).astype(np.float16).astype(np.float32)  # mistake: no scaling
+
+
+def half_store_identity(v, sigma):
+    return np.asarray(v, dtype=np.float32)  # mistake: the basis is never rounded
+
+
 MUTATIONS = {
     "spmv_drop_last": ("spmv", spmv_drop_last),
     "spmv_row_index": ("spmv", spmv_row_index),
@@ -154,6 +162,8 @@ MUTATIONS = {
     "poly_apply_f64_always": ("poly_apply", poly_apply_f64_always),
     "bjac_transposed": ("bjac_apply", bjac_transposed),
     "bjac_short_blocks": ("bjac_apply", bjac_short_blocks),
+    "half_store_unscaled": ("half_store", half_store_unscaled),
+    "half_store_identity": ("half_store", half_store_identity),
 }
 
 FAST_CHECKS = [c for c in pins.ALL_CHECKS if c.__name__ not in
