@@ -281,6 +281,18 @@ def single_system(args, kind):
                                       half_basis=True, prof=fam)[1]
                 half[fam + "_gbs"] = round(rp.prof_bytes / (rp.prof_ms * 1e-3) / 1e9, 1) if rp.prof_ms else None
                 half[fam + "_ms"] = round(rp.prof_ms, 3)
+    if degree and prob.A.n > 1024:
+        log("bench: GMRES-IR + float32 polynomial with the float16 basis")
+        x.zero_()
+        t0 = time.perf_counter()
+        _, rh = G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir, P=P32,
+                                 half_basis=True)
+        t_h = time.perf_counter() - t0
+        xh16 = x.cpu().numpy()
+        rel16 = float(np.linalg.norm(prob.b - host_csr(prob.A) @ xh16) / np.linalg.norm(prob.b))
+        half = {"seconds": round(t_h, 5), "iters": rh.iters, "cycles": rh.cycles, "rel_res": rel16,
+                "speedup_vs_fp64": round(t_64 / t_h, 3), "speedup_vs_f32_basis": round(t_ir / t_h, 3)}
+        assert rh.converged and rel16 <= 1e-10, half
     mixed = None
     if degree:
         # the middle option of §V-C: float64 GMRES with the float32 polynomial

@@ -99,14 +99,15 @@ typedef struct {
  * the solver counts such a restart in result->loss_of_accuracy and goes on
  * from the explicit residual: the correction §V-F proposes.  GMRES-IR ignores it. */
 #define GMR_FLAG_STOP_ON_LOSS 4
-/* gmr_params.flags: GMRES-IR (gmres_ir_solve without a preconditioner) stores
- * the inner Krylov basis in IEEE float16, column j as half(sigma * v_j) with
+/* gmr_params.flags: GMRES-IR (gmres_ir_solve, with or without a preconditioner)
+ * stores the inner Krylov basis in IEEE float16, column j as half(sigma * v_j) with
  * the power of two sigma ~ sqrt(n); all arithmetic stays float32 and the outer
  * loop float64.  A third precision, the future work of §VI: it halves the
  * bytes of the basis that CGS2 streams, and each cycle's correction is then
  * accurate to about 1e-3, which the outer float64 loop absorbs (more cycles
  * only when a cycle would otherwise reduce the residual by much more).
- * GMR_ERR_UNSUPPORTED with a preconditioner or in the other solvers. */
+ * The preconditioner is applied to the float32 vector before rounding.
+ * GMR_ERR_UNSUPPORTED in the other solvers. */
 #define GMR_FLAG_HALF_BASIS 8
 
 typedef struct {

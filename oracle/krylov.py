@@ -227,7 +227,8 @@ def gmres_ir(A, b, x0, m: int, tol: float, max_iters: int,
              half_basis: bool = False) -> GmresOutcome:
     n = A.n
     # third precision (§VI): the basis used by Gram-Schmidt and the update is
-    # stored in float16; the SpMV takes the float32 vector before rounding
+    # stored in float16; the preconditioner and the SpMV take the float32
+    # vector before rounding
     store = (lambda v: half_store(v, half_sigma(n))) if half_basis else (lambda v: v)
     b = np.asarray(b, dtype=np.float64)
     bnorm = float(np.linalg.norm(b))
@@ -250,7 +251,7 @@ def gmres_ir(A, b, x0, m: int, tol: float, max_iters: int,
         g[0] = float(beta0)
         k = 0
         for j in range(m):
-            z = prec32(V[:, j]) if prec32 else vj
+            z = prec32(vj) if prec32 else vj
             w = spmv(A, z, f32)
             w, h1, h2, beta = cgs2(V, j + 1, w)
             H[: j + 1, j] = h1.astype(np.float64) + h2.astype(np.float64)

@@ -609,8 +609,8 @@ static gmr_status solve_impl(const SolveArgs& a) {
   const bool mixed = poly && a.P->dtype == GMR_F32 && sizeof(TI) == 8;
   const gmr_csr* Ap = a.Aprec ? a.Aprec : a.Ain;
   const bool half = (prm.flags & GMR_FLAG_HALF_BASIS) != 0;
-  if (half && (poly || sizeof(TI) != 4 || sizeof(TO) != 8))
-    return fail(GMR_ERR_UNSUPPORTED, "GMR_FLAG_HALF_BASIS needs GMRES-IR without a preconditioner");
+  if (half && (sizeof(TI) != 4 || sizeof(TO) != 8))
+    return fail(GMR_ERR_UNSUPPORTED, "GMR_FLAG_HALF_BASIS is a GMRES-IR option");
   if (poly && a.P->kind == kPrecBjac && a.P->n != n)
     return fail(GMR_ERR_INVALID, "block Jacobi preconditioner built for another order n");
   Ws ws{(char*)a.ws, small_layout(n)};
@@ -715,7 +715,22 @@ static gmr_status solve_impl(const SolveArgs& a) {
     for (int j = 0; j < mc; ++j) {
       TI* vj = V + (size_t)j * B.ldv;
       TI* wn = W[cur ^ 1];
-      if (poly) {
+      if (poly && half) {
+        if constexpr (sizeof(TI) == 4 && sizeof(TO) == 8) {
+          // v_j in float32 (in U, free until the end of the cycle) for the
+          // preconditioner, float16 into the basis
+          half_t* Vh = reinterpret_cast<half_t*>(V);
+          TI* Z = ws.at<TI>(B.Z);
+          hb_scale_kernel<<<stream_grid(n), kBlock, 0, c.s>>>(n, W[cur], cs.inv_beta, sigma,
+                                                             Vh + (size_t)j * B.ldv, U, done);
+          GMR_TRY(check_launch("hb_scale_kernel"));
+          GMR_TRY(apply_prec(U, Z, done));
+          GMR_TRY(launch_spmv<TI>(c, a.Ain, Z, nullptr, nullptr, wn, done));
+          GMR_TRY(hb_cgs2_passes(c, n, j + 1, Vh, B.ldv, wn, ws, cs, mc - 1, 1.0f / sigma, done));
+        }
+        cur ^= 1;
+        continue;
+      } else if (poly) {
         TI* Z = ws.at<TI>(B.Z);
         scale_kernel<TI><<<stream_grid(n), kBlock, 0, c.s>>>(n, W[cur], cs.inv_beta, vj, done);
         GMR_TRY(check_launch("scale_kernel"));
@@ -742,15 +757,23 @@ static gmr_status solve_impl(const SolveArgs& a) {
     }
     if (poly) {
       TI* Z = ws.at<TI>(B.Z);
-      solution_update_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, V, B.ldv, cs.y, st_dev, U, nullptr);
-      GMR_TRY(check_launch("solution_update_kernel"));
+      if (half) {
+        if constexpr (sizeof(TI) == 4 && sizeof(TO) == 8) {
+          hb_solution_update_kernel<<<stream_grid(n), kBlock, 0, c.s>>>(
+              n, reinterpret_cast<const half_t*>(V), B.ldv, cs.y, 1.0f / sigma, st_dev, U, nullptr);
+          GMR_TRY(check_launch("hb_solution_update_kernel"));
+        }
+      } else {
+        solution_update_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, V, B.ldv, cs.y, st_dev, U, nullptr);
+        GMR_TRY(check_launch("solution_update_kernel"));
+      }
       GMR_TRY(apply_prec(U, Z, nullptr));
       axpy_gamma_kernel<TI, TO><<<stream_grid(n), kBlock, 0, c.s>>>(n, Z, st_dev, x);
       GMR_TRY(check_launch("axpy_gamma_kernel"));
     } else if (half) {
       if constexpr (sizeof(TI) == 4 && sizeof(TO) == 8) {
         hb_solution_update_kernel<<<stream_grid(n), kBlock, 0, c.s>>>(n, reinterpret_cast<const half_t*>(V), B.ldv,
-                                                                     cs.y, 1.0f / sigma, st_dev, x);
+                                                                     cs.y, 1.0f / sigma, st_dev, nullptr, x);
         GMR_TRY(check_launch("hb_solution_update_kernel"));
       }
     } else {

@@ -221,10 +221,27 @@ __global__ __launch_bounds__(kBlock) void hb_update_kernel(int n, int j, const h
   }
 }
 
-// x += gamma * double(V_k y) with V_k y formed in float32 (k from the status).
+// With a right preconditioner: v_j = x * scale in float32 for the
+// preconditioner (out), and half(sigma * v_j) into the basis.
+__global__ __launch_bounds__(kBlock) void hb_scale_kernel(int n, const float* __restrict__ x,
+                                                          const double* __restrict__ scale, float sigma,
+                                                          half_t* __restrict__ vout, float* __restrict__ out,
+                                                          const int* __restrict__ done) {
+  if (done && *done) return;
+  const float s = float(*scale);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const float v = x[i] * s;
+    out[i] = v;
+    vout[i] = half_t(v * sigma);
+  }
+}
+
+// u = V_k y formed in float32 (k from the status); then x += gamma * double(u),
+// or, when u_out is given, u is stored there (a preconditioner follows).
 __global__ __launch_bounds__(kBlock) void hb_solution_update_kernel(int n, const half_t* __restrict__ V,
                                                                     int64_t ldv, const double* __restrict__ y,
                                                                     float inv_sigma, const Status* __restrict__ st,
+                                                                    float* __restrict__ u_out,
                                                                     double* __restrict__ x) {
   __shared__ float s_y[kMaxCols];
   const int k = st->k;
@@ -234,7 +251,8 @@ __global__ __launch_bounds__(kBlock) void hb_solution_update_kernel(int n, const
   for (int r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
     float s = 0.f;
     for (int c = 0; c < k; ++c) s += float(V[(size_t)c * ldv + r]) * s_y[c];
-    x[r] += gam * double(s);
+    if (u_out) u_out[r] = s;
+    else x[r] += gam * double(s);
   }
 }
 
