@@ -138,6 +138,14 @@ __global__ __launch_bounds__(kBlock) void hb_update_dots_kernel(int n, int j, co
     }
     if (full) *reinterpret_cast<fvec2_t*>(w + r) = wv;
     else if (one) w[r] = wv.x;
+    // convert the packed values again for the dots rather than keep 2K float
+    // copies live from the update (which would halve the resident waves)
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      unsigned u = __builtin_bit_cast(unsigned, v[c]);
+      asm volatile("" : "+v"(u));
+      v[c] = __builtin_bit_cast(hvec2_t, u);
+    }
     const fvec2_t ws = wv * inv_sigma;
     float a[K];
 #pragma unroll
