@@ -110,13 +110,19 @@ def dependent_columns(G: np.ndarray, tau: float = DEP_TAU) -> np.ndarray:
 
 
 START_TAU = 1e-12
+# Dependency threshold of a start block with a float32 inner solve: the kept
+# columns then have parts outside the span of the earlier ones of relative
+# squared norm > 1e-3, which bounds the block's condition number to the range
+# (about u^-1/2 in float32) where Cholesky QR twice is reliable; float64 keeps 1e-5.
+START_DEP_TAU_F32 = 1e-3
 
 
 def start_block(W: np.ndarray, Z: np.ndarray):
     """Orthonormal start block of a cycle: columns of W that (nearly) depend on
     earlier ones are replaced by the matching columns of the random block Z
     before Cholesky QR twice; R0 = V0^T W then represents every column of W."""
-    dep = dependent_columns((W.T @ W).astype(np.float64))
+    tau = START_DEP_TAU_F32 if W.dtype == np.float32 else DEP_TAU
+    dep = dependent_columns((W.T @ W).astype(np.float64), tau)
     Wp = W.copy()
     Wp[:, dep] = Z[:, dep].astype(W.dtype)
     V0, _, ok = cholqr2(Wp, START_TAU)

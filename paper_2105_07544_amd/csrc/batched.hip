@@ -1358,7 +1358,11 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
     bstart_kernel<T><<<nt, kBlock, 0, R.s>>>(tl, st, R64, gam, W);
     BT(launch_check("bstart_kernel"));
     BT(dots<T>(R, W, 1, W, Cd, nullptr));
-    bdep_kernel<<<ns, kBlock, 0, R.s>>>(st, Cd, R.L.cstride, R.at<int>(R.L.dep), 1e-5);
+    // a start column is replaced when its part outside the span of the earlier
+    // kept columns has relative squared norm <= tau: with a float32 inner solve
+    // 1e-3, which keeps the start block's condition number within the range
+    // (about u^-1/2) where Cholesky QR twice in float32 is reliable
+    bdep_kernel<<<ns, kBlock, 0, R.s>>>(st, Cd, R.L.cstride, R.at<int>(R.L.dep), sizeof(T) == 4 ? 1e-3 : 1e-5);
     BT(launch_check("bdep_kernel"));
     breplace_kernel<T><<<nt, kBlock, 0, R.s>>>(tl, st, R.at<int>(R.L.dep), W, Z, Tm);
     BT(launch_check("breplace_kernel"));
