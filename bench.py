@@ -599,7 +599,12 @@ def batch(args):
     bt = G.Batch([s["A"].n for s in systems], restart=m)
     bt.set_graph(bool(args.graph))
     ws = G.alloc_workspace(bt.workspace_bytes(), dev)
-    tiling = bt.autotune(ws)
+    if args.tiling:
+        tr, gb = (int(v) for v in args.tiling.split(","))
+        bt.set_tiling(tr, gb)
+        tiling = (tr, gb, None)
+    else:
+        tiling = bt.autotune(ws)
     log(f"bench: autotuned tiling {tiling}")
     Bd = torch.from_numpy(B).to(dev)
     Zd = torch.from_numpy(Z).to(dev)
@@ -713,6 +718,7 @@ def main():
     ap.add_argument("--fd-max", type=int, default=0, help="fd: last switch point (0: float64 GMRES's count)")
     ap.add_argument("--degrees", default="10,20,30,40,50,60,70", help="prec32: polynomial degrees")
     ap.add_argument("--blocks", default="1,42", help="bjac: block sizes")
+    ap.add_argument("--tiling", default="", help="batch: 'rows,variant' instead of the autotuner")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")

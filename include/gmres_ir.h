@@ -336,11 +336,13 @@ gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* gro
  * Results are identical to the eager launches. */
 gmr_status batch_set_graph(gmr_batch* b, int32_t on);
 
-/* Times the block Gram-Schmidt contraction pair (dots and update at about
- * (m+1)/8, (m+1)/2 and 7(m+1)/8 blocks, every system active) for every candidate tiling (tile rows 512,
- * 1024, 2048, 4096 x dots variants 4, 8, 16, 2, 3, 5, 6, 7) on the batch's own workspace (its
- * contents are overwritten), keeps the fastest and reports it: *best_ms is
- * the fastest of five timed repetitions (best_* may be NULL).  Synchronous. */
+/* Chooses the tiling by timing the block Gram-Schmidt contractions at about
+ * (m+1)/8, (m+1)/2 and 7(m+1)/8 blocks, every system active, on the batch's
+ * own workspace (its contents are overwritten), in two stages: the tile rows
+ * (512, 1024, 2048, 4096) by the dots and update pair with the staged dots
+ * variant 7, then the dots variant (4, 8, 16, 2, 3, 5, 6, 7) at those rows by
+ * the dots alone.  Keeps the choice; *best_ms is the fastest of five timed
+ * repetitions of the pair at the chosen rows (best_* may be NULL).  Synchronous. */
 gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,
                           int32_t* best_group_blocks, double* best_ms, void* stream);
 

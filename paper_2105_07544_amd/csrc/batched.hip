@@ -1495,10 +1495,9 @@ gmr_status batch_gmres_solve(gmr_batch* b, const gmr_csr* A64, const double* B, 
                             sys_cycles, sys_rel_res, stream);
 }
 
-// Times the block Gram-Schmidt contraction pair (dots + update) at three basis
-// sizes, about (m+1)/8, (m+1)/2 and 7(m+1)/8 blocks, for every candidate
-// tiling on the batch's own buffers and keeps the fastest.  The workspace is
-// the solve's; its contents are overwritten.
+// Chooses the tiling by timing the block Gram-Schmidt contractions at three
+// basis sizes, about (m+1)/8, (m+1)/2 and 7(m+1)/8 blocks, on the batch's own
+// buffers (the workspace is the solve's; its contents are overwritten).
 gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best_tile_rows,
                           int32_t* best_group_blocks, double* best_ms, void* stream) {
   if (!b) return gmr::fail(GMR_ERR_INVALID, "batch_autotune: null batch");
@@ -1518,41 +1517,54 @@ gmr_status batch_autotune(gmr_batch* b, void* ws, size_t ws_bytes, int32_t* best
   const int nbs[3] = {std::max(1, (b->m + 1) / 8), std::max(1, (b->m + 1) / 2), std::max(1, (b->m + 1) * 7 / 8)};
   const int cand_rows[] = {512, 1024, 2048, 4096};
   const int cand_gb[] = {4, 8, 16, kDotsW2x8, kDotsW4x4, kDotsW4x8, kDotsV8, kDotsV16};
+  // The fastest of `reps` timed repetitions (after one warm-up) of the dots,
+  // and with `upd` the block update too, at the three basis sizes.
+  auto time_pair = [&](int reps, bool upd, float* out) -> gmr_status {
+    float ms = 1e30f;
+    for (int rep = 0; rep <= reps; ++rep) {
+      if (hipEventRecord(e0, R.s) != hipSuccess) return GMR_ERR_HIP;
+      for (int nb : nbs) {
+        BT(dots<float>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd), R.at<float>(R.L.Cf)));
+        if (upd) BT((gemm<float, kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))));
+      }
+      if (hipEventRecord(e1, R.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return GMR_ERR_HIP;
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      if (rep > 0) ms = std::min(ms, t);
+    }
+    *out = ms;
+    return GMR_OK;
+  };
+  // Two stages: the tile size by the dots and update together (with the staged
+  // dots variant), then the dots variant at that tile size by the dots alone,
+  // whose differences (a few per cent) the pair would blur with run-to-run noise.
   double best = 1e30;
-  int bt = b->tile_rows, bg = b->gb;
+  int bt = b->tile_rows, bg = kDotsV16;
   gmr_status status = GMR_OK;
   for (int tr : cand_rows) {
+    build_tiles(b, tr);
+    b->gb = kDotsV16;
+    float ms = 0.f;
+    if ((status = upload_tables(R)) != GMR_OK || (status = time_pair(5, true, &ms)) != GMR_OK) break;
+    if (ms < best) {
+      best = ms;
+      bt = tr;
+    }
+  }
+  if (status == GMR_OK) {
+    build_tiles(b, bt);
+    status = upload_tables(R);
+    float best_d = 1e30f;
     for (int g : cand_gb) {
-      build_tiles(b, tr);
-      b->gb = g;
-      if ((status = upload_tables(R)) != GMR_OK) break;
-      // the fastest of five timed repetitions after one warm-up: the minimum is
-      // the least noisy estimate of a launch pair's cost
-      float ms = 1e30f;
-      for (int rep = 0; rep < 6; ++rep) {
-        if (hipEventRecord(e0, R.s) != hipSuccess) { status = GMR_ERR_HIP; break; }
-        for (int nb : nbs) {
-          if ((status = dots<float>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.W), R.at<double>(R.L.Cd),
-                                    R.at<float>(R.L.Cf))) != GMR_OK)
-            break;
-          if ((status = gemm<float, kSub>(R, R.at<float>(R.L.V), nb, R.at<float>(R.L.Cf), R.at<float>(R.L.W))) !=
-              GMR_OK)
-            break;
-        }
-        if (status != GMR_OK) break;
-        if (hipEventRecord(e1, R.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { status = GMR_ERR_HIP; break; }
-        float t = 0.f;
-        (void)hipEventElapsedTime(&t, e0, e1);
-        if (rep > 0) ms = std::min(ms, t);
-      }
       if (status != GMR_OK) break;
-      if (ms < best) {
-        best = ms;
-        bt = tr;
+      b->gb = g;
+      float ms = 0.f;
+      if ((status = time_pair(9, false, &ms)) != GMR_OK) break;
+      if (ms < best_d) {
+        best_d = ms;
         bg = g;
       }
     }
-    if (status != GMR_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
