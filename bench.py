@@ -338,7 +338,7 @@ def single_system(args, kind):
     }
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        prec32, ks = None, (1, 4, 10)
+        prec32, ks = None, (3, 10, 24)
         import oracle as O
         if degree:
             # the oracle builds its own float32 polynomial from the same start vector
