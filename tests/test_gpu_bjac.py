@@ -139,3 +139,15 @@ def test_bjac_full_size_sampled_blocks():
         B = O.diagonal_block(p.A, r0, r1).astype(np.float32)
         ref = np.linalg.solve(B, v[r0:r1].astype(np.float32)).astype(np.float64)
         assert np.abs(y[r0:r1] - ref).max() <= 2e-5 * np.abs(ref).max(), b
+
+
+def test_bjac_graph_replay_is_bitwise_eager():
+    p = W.config3_convdiff(N=48, restart=12, degree=0)
+    A64 = G.DeviceCSR.from_host(p.A, DEV)
+    A32 = A64.to_f32()
+    J = G.bjac_prec_setup(A32, 42)
+    out = [G.gmres_ir_solve(A64, A32, tdev(p.b, np.float64), restart=12, max_iters=20000, P=J, graph=g)
+           for g in (False, True, True)]
+    for x, r in out[1:]:
+        assert r.converged and r.iters == out[0][1].iters
+        assert np.array_equal(host(x), host(out[0][0]))

@@ -126,3 +126,16 @@ def test_fd_laplace3d200_one_switch_point_full_size():
     xh = host(x)
     rel = np.linalg.norm(p.b - scipy_csr(p.A) @ xh) / np.linalg.norm(p.b)
     assert rel <= 1e-10, rel
+
+
+def test_fd_graph_and_persistent_flags():
+    """GMRES-FD under graph replay gives the eager bits; the single-block cycle
+    (n <= 1024) reaches the same tolerance with the same iteration split."""
+    A, b, _ = _problem()
+    A64 = G.DeviceCSR.from_host(A, DEV)
+    A32 = A64.to_f32()
+    x0, r0, f0 = G.gmres_fd_solve(A64, A32, t64(b), 60, restart=20, tol=1e-10, max_iters=20000)
+    x1, r1, f1 = G.gmres_fd_solve(A64, A32, t64(b), 60, restart=20, tol=1e-10, max_iters=20000, graph=True)
+    assert np.array_equal(host(x0), host(x1)) and r0.iters == r1.iters and f0.iters == f1.iters == 60
+    x2, r2, f2 = G.gmres_fd_solve(A64, A32, t64(b), 60, restart=20, tol=1e-10, max_iters=20000, persistent=True)
+    assert r2.converged and f2.iters == 60 and abs(r2.iters - r0.iters) <= 20

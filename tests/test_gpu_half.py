@@ -126,3 +126,14 @@ def test_half_basis_config2_full_size():
     say(r.iters, r.cycles, r.seconds, "float32 basis", r32.iters, r32.cycles, r32.seconds)
     assert r.converged and rel_res(p.A, p.b, host(x)) <= 1e-10
     assert r.cycles <= 1.2 * r32.cycles
+
+
+def test_half_basis_ignores_the_persistent_flag():
+    # the single-block cycle has no float16 form: the flag is ignored, same bits
+    A = W.laplace2d(20)
+    b = W.host_matvec(A, W.uniform_pm1(5, A.n))
+    A64 = G.DeviceCSR.from_host(A, DEV)
+    A32 = A64.to_f32()
+    x0, r0 = G.gmres_ir_solve(A64, A32, t64(b), restart=20, half_basis=True)
+    x1, r1 = G.gmres_ir_solve(A64, A32, t64(b), restart=20, half_basis=True, persistent=True)
+    assert r0.converged and r0.iters == r1.iters and np.array_equal(host(x0), host(x1))
