@@ -130,6 +130,18 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, kernel: str, pa
     for r in rows:
         print(f"| `{r[0]}` | {r[1]} | {r[2]:.1f} | {r[3]:.1f} | {r[4]:.4g} |")
     print(f"\nall {kernel} launches ({', '.join(patterns)}): {cnt}, mean HBM bytes per launch {per_launch:.6g}")
+    # the SpMV in both precisions (the cache model of §V-D): reads and writes apart
+    sp = [(p, [n for n in f if p in n]) for p in ("spmv_kernel<float", "spmv_kernel<double")]
+    if all(names for _, names in sp):
+        print("\n| SpMV | launches | HBM bytes read/launch | HBM bytes written/launch |")
+        print("|---|---|---|---|")
+        reads = {}
+        for p, names in sp:
+            vf = [v for n in names for v in f[n]]
+            vw = [v for n in names for v in w.get(n, [])]
+            reads[p] = 1024.0 * ff * sum(vf) / len(vf)
+            print(f"| `{p}>` | {len(vf)} | {reads[p]:.4g} | {1024.0 * fw * sum(vw) / max(1, len(vw)):.4g} |")
+        print(f"\nread ratio float64 / float32: {reads['spmv_kernel<double'] / reads['spmv_kernel<float']:.3f}")
 
 
 def cpu_threads():
