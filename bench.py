@@ -22,6 +22,7 @@ Other workloads (each prints its own line; the default line is the one above):
              a float64 or a float32 polynomial (loss of accuracy), and GMRES-IR
   bjac       block Jacobi (block 1 and 42) on the 2500^2 convection-diffusion
              matrix: GMRES-IR with float32 blocks vs float64 GMRES
+  restart    restart lengths 25..400 on the 3D Laplacian 150^3 (b = ones)
 
 Extra fields: the float64 GMRES time on the same GPU and the ratio,
 per-kernel-family time and GB/s (the analogue of the paper's Table I), the
@@ -592,6 +593,62 @@ def bjac_leg(args):
     }
 
 
+def restart_sweep(args):
+    """The restart-length study of §V-E on the 3D Laplacian 150^3 (b = ones):
+    float64 GMRES(m) and GMRES(m)-IR for m = 25 .. 400."""
+    import numpy as np
+    import torch
+
+    import paper_2105_07544_amd as G
+    import workloads as W
+
+    dev = "cuda:0"
+    N = args.grid or 150
+    log("bench: building the workload")
+    prob = W.fd_laplace3d(N)
+    A64 = G.DeviceCSR.from_host(prob.A, dev)
+    A32 = A64.to_f32()
+    b = torch.from_numpy(prob.b).to(dev)
+    x = torch.zeros_like(b)
+    Ah = host_csr(prob.A)
+    ms = [int(v) for v in args.restarts.split(",")]
+    ws = G.alloc_workspace(G.workspace_bytes(prob.A.n, max(ms), G.GMR_F64), dev)
+
+    def run(fn):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, r = fn()
+        sec = time.perf_counter() - t0
+        rel = float(np.linalg.norm(prob.b - Ah @ x.cpu().numpy()) / np.linalg.norm(prob.b))
+        return {"status": r.status_name, "iters": r.iters, "cycles": r.cycles, "seconds": round(sec, 4),
+                "rel_res": rel}
+
+    rows = []
+    G.gmres_ir_solve(A64, A32, b, x, restart=50, tol=1e-10, max_iters=20000, ws=ws)  # warm-up
+    for m in ms:
+        row = {"restart": m,
+               "f64": run(lambda: G.gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=20000, ws=ws)),
+               "ir": run(lambda: G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=20000,
+                                                  stagnation_cycles=20, ws=ws)),
+               "ir_half_basis": run(lambda: G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=20000,
+                                                             stagnation_cycles=20, ws=ws, half_basis=True))}
+        row["ir_speedup_vs_fp64"] = round(row["f64"]["seconds"] / row["ir"]["seconds"], 3)
+        rows.append(row)
+        log("bench: " + json.dumps(row))
+    ok = [r for r in rows if r["ir"]["status"] == "GMR_OK"]
+    best = min(ok, key=lambda r: r["ir"]["seconds"])
+    return {
+        "metric": METRIC, "value": best["ir"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1e3 * best["ir"]["seconds"], 3), "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": (f"restart sweep {ms}: float64 GMRES(m) vs GMRES(m)-IR, 3D Laplacian 6/-1 on {N}^3 "
+                                f"(n={prob.A.n}), b=ones, x0=0, tol 1e-10"),
+                   "n": prob.A.n, "nnz": prob.A.nnz, "tol": 1e-10},
+        "best_ir_restart": best["restart"], "sweep": rows,
+    }
+
+
 def batch(args):
     import numpy as np
     import torch
@@ -721,7 +778,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace3d",
-                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd", "prec32", "bjac"])
+                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd", "prec32", "bjac",
+                             "restart"])
     ap.add_argument("--grid", type=int, default=0, help="grid side (0: the workload's own)")
     ap.add_argument("--restart", type=int, default=0, help="restart length (0: the workload's own)")
     ap.add_argument("--train", type=int, default=192, help="predictor: training systems")
@@ -730,6 +788,7 @@ def main():
     ap.add_argument("--fd-max", type=int, default=0, help="fd: last switch point (0: float64 GMRES's count)")
     ap.add_argument("--degrees", default="10,20,30,40,50,60,70", help="prec32: polynomial degrees")
     ap.add_argument("--blocks", default="1,42", help="bjac: block sizes")
+    ap.add_argument("--restarts", default="25,50,100,200,300,400", help="restart: restart lengths")
     ap.add_argument("--tiling", default="", help="batch: 'rows,variant' instead of the autotuner")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -767,6 +826,8 @@ def main():
         out = prec32_sweep(args)
     elif args.workload == "bjac":
         out = bjac_leg(args)
+    elif args.workload == "restart":
+        out = restart_sweep(args)
     else:
         out = single_system(args, args.workload)
     print(json.dumps(out), flush=True)

@@ -70,7 +70,7 @@ typedef enum {
 } gmr_prof_kernel;
 
 typedef struct {
-  int32_t restart;           /* m, 1 <= m <= 256 (§III-A "restart length")                 */
+  int32_t restart;           /* m, 1 <= m <= 512 (§III-A "restart length")                 */
   double tol;                /* relative residual tolerance, > 0                           */
   int64_t max_iters;         /* cap on inner iterations (> 0)                              */
   int32_t max_cycles;        /* cap on restarts, 0 = none                                  */
@@ -150,7 +150,7 @@ gmr_status spmv(const gmr_csr* A, const void* x, void* y, void* stream);
  * beta = ||w||, w /= beta.  V: device, n x k column-major, leading dim ldv.
  * w: device, n entries, overwritten with the normalised vector (left as is
  * when beta is 0).  h: device float64, k+1 entries: h[0..k-1] = h1 + h2 and
- * h[k] = beta.  1 <= k <= 256.  dtype selects float32 or float64 data.
+ * h[k] = beta.  1 <= k <= 512.  dtype selects float32 or float64 data.
  * ws: device workspace of gmres_workspace_bytes(n, {restart >= k}, dtype, 0)
  * bytes.  Asynchronous. */
 gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t ldv, void* w,

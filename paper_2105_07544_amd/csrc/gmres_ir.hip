@@ -249,8 +249,10 @@ static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, con
       cgs_dots_kernel<T, 32, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
     else if (j <= 64)
       cgs_dots_kernel<T, 64, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
-    else
+    else if (j <= 256)
       cgs_dots_kernel<T, 64, 4><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+    else
+      cgs_dots_kernel<T, 64, 8><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
     GMR_TRY(check_launch("cgs_dots_kernel"));
     GMR_TRY(c.end(GMR_PROF_CGS_DOTS, (double)(j + 1) * n * sizeof(T)));
     finish_cols_kernel<T><<<j, kBlock, 0, c.s>>>(G, part, hd, ht, done);
@@ -265,8 +267,10 @@ static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, con
     cgs_dots4_kernel<T, 32, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
   else if (j <= 64)
     cgs_dots4_kernel<T, 64, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
-  else
+  else if (j <= 256)
     cgs_dots4_kernel<T, 64, 4><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+  else
+    cgs_dots4_kernel<T, 64, 8><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
   GMR_TRY(check_launch("cgs_dots_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_DOTS, (double)(j + 1) * n * sizeof(T)));
   finish_cols_kernel<T><<<j, kBlock, 0, c.s>>>(G, part, hd, ht, done);
@@ -341,7 +345,8 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
   else if (j <= 16) GMR_HD(16, 1);
   else if (j <= 32) GMR_HD(32, 1);
   else if (j <= 64) GMR_HD(64, 1);
-  else GMR_HD(64, 4);
+  else if (j <= 256) GMR_HD(64, 4);
+  else GMR_HD(64, 8);
   GMR_TRY(check_launch("hb_dots_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_DOTS, vb + 4.0 * n));
   finish_cols_kernel<float><<<j, kBlock, 0, c.s>>>(G, part, cs.h1d, ws.h1t<float>(), done);
@@ -353,7 +358,8 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
                                                                part, done);
     GMR_TRY(check_launch("hb_update_kernel"));
     GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, vb + 8.0 * n));
-    GMR_HD(64, 4);
+    if (j <= 256) GMR_HD(64, 4);
+    else GMR_HD(64, 8);
     GMR_TRY(check_launch("hb_dots_kernel"));
   } else {
 #define GMR_HUD(K) \
@@ -539,7 +545,7 @@ struct SolveArgs {
 static gmr_status check_params(const gmr_params* p) {
   if (!p) return fail(GMR_ERR_INVALID, "null params");
   if (p->restart < 1) return fail(GMR_ERR_INVALID, "restart must be >= 1");
-  if (p->restart > kMaxCols) return fail(GMR_ERR_UNSUPPORTED, "restart > 256 is not supported");
+  if (p->restart > kMaxCols) return fail(GMR_ERR_UNSUPPORTED, "restart > 512 is not supported");
   if (!(p->tol > 0.0)) return fail(GMR_ERR_INVALID, "tol must be > 0");
   if (p->max_iters <= 0) return fail(GMR_ERR_INVALID, "max_iters must be > 0");
   if (p->max_cycles < 0 || p->stagnation_cycles < 0) return fail(GMR_ERR_INVALID, "negative cycle cap");
@@ -965,7 +971,7 @@ gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t
                      double* h, void* ws, size_t ws_bytes, void* stream) {
   if (dtype != GMR_F32 && dtype != GMR_F64) return fail(GMR_ERR_INVALID, "cgs2_orth: unknown dtype");
   if (n <= 0 || k < 1) return fail(GMR_ERR_INVALID, "cgs2_orth: need n > 0 and k >= 1");
-  if (k > kMaxCols) return fail(GMR_ERR_UNSUPPORTED, "cgs2_orth: k > 256 is not supported");
+  if (k > kMaxCols) return fail(GMR_ERR_UNSUPPORTED, "cgs2_orth: k > 512 is not supported");
   if (ldv < n) return fail(GMR_ERR_INVALID, "cgs2_orth: ldv < n");
   if (!V || !w || !h) return fail(GMR_ERR_INVALID, "cgs2_orth: null pointer");
   const Small S = small_layout(n);

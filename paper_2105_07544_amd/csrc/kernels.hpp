@@ -27,7 +27,7 @@ constexpr int kSpmvChunk = 2048;
 // Upper bound on the number of blocks of a reduction kernel (partials per column).
 constexpr int kMaxRedBlocks = 1024;
 // Basis columns (j) supported by the kernels; H has restart+1 rows.
-constexpr int kMaxCols = 256;
+constexpr int kMaxCols = 512;
 // Column partials are stored column-major: partial[c * kPartPitch + block], so
 // the finish kernel of column c reads one contiguous run.
 constexpr int kPartPitch = kMaxRedBlocks;
@@ -909,7 +909,8 @@ __device__ __forceinline__ void small_cgs2(int n, int j, const T* V, int64_t ldv
   else if (j <= 16) cgs_dots_body<T, 16, 1>(n, j, V, ldv, w, partial, nullptr);
   else if (j <= 32) cgs_dots_body<T, 32, 1>(n, j, V, ldv, w, partial, nullptr);
   else if (j <= 64) cgs_dots_body<T, 64, 1>(n, j, V, ldv, w, partial, nullptr);
-  else cgs_dots_body<T, 64, 4>(n, j, V, ldv, w, partial, nullptr);
+  else if (j <= 256) cgs_dots_body<T, 64, 4>(n, j, V, ldv, w, partial, nullptr);
+  else cgs_dots_body<T, 64, 8>(n, j, V, ldv, w, partial, nullptr);
   __syncthreads();
   take_cols<T>(j, partial, cs.h1d, h1t);
   __syncthreads();
@@ -920,7 +921,8 @@ __device__ __forceinline__ void small_cgs2(int n, int j, const T* V, int64_t ldv
   else {
     cgs_update_body<T>(n, j, V, ldv, h1t, w, nullptr);
     __syncthreads();
-    cgs_dots_body<T, 64, 4>(n, j, V, ldv, w, partial, nullptr);
+    if (j <= 256) cgs_dots_body<T, 64, 4>(n, j, V, ldv, w, partial, nullptr);
+    else cgs_dots_body<T, 64, 8>(n, j, V, ldv, w, partial, nullptr);
   }
   __syncthreads();
   take_cols<T>(j, partial, cs.h2d, h2t);

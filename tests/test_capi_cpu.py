@@ -50,8 +50,10 @@ def test_workspace_query():
     c = G.workspace_bytes(1000, 100, G.GMR_F32)
     d = G.workspace_bytes(1000, 50, G.GMR_F32, True)
     assert 0 < a < b and a < c and a < d
-    p = _capi.gmr_params(300, 1e-10, 10, 0, 0, 0, 0)
+    p = _capi.gmr_params(600, 1e-10, 10, 0, 0, 0, 0)
     assert G.lib().gmres_workspace_bytes(1000, C.byref(p), 0, 0) == 0
+    p = _capi.gmr_params(512, 1e-10, 10, 0, 0, 0, 0)
+    assert G.lib().gmres_workspace_bytes(1000, C.byref(p), 0, 0) > c
 
 
 def test_argument_errors_before_device_work():
@@ -69,7 +71,7 @@ def test_argument_errors_before_device_work():
     assert lib.gmres_solve(C.byref(A), None, 8, 16, C.byref(bad), None, 0, C.byref(res), None, None) == -1
     bad = _capi.gmr_params(50, -1.0, 100, 0, 0, 0, 0)
     assert lib.gmres_solve(C.byref(A), None, 8, 16, C.byref(bad), None, 0, C.byref(res), None, None) == -1
-    bad = _capi.gmr_params(257, 1e-10, 100, 0, 0, 0, 0)
+    bad = _capi.gmr_params(513, 1e-10, 100, 0, 0, 0, 0)
     assert lib.gmres_solve(C.byref(A), None, 8, 16, C.byref(bad), None, 0, C.byref(res), None, None) == -5
     # dtype mismatch for GMRES-IR
     assert lib.gmres_ir_solve(C.byref(A), C.byref(A), None, 8, 16, C.byref(p), None, 0, C.byref(res),
@@ -77,7 +79,7 @@ def test_argument_errors_before_device_work():
     # workspace too small is found before any launch: gmres_solve checks it first
     with pytest.raises(G.GmresError):
         _capi.check(lib.cgs2_orth(0, 10, 0, 1, 10, 1, 1, None, 0, None))
-    assert lib.cgs2_orth(0, 10, 300, 1, 10, 1, 1, None, 0, None) == -5
+    assert lib.cgs2_orth(0, 10, 600, 1, 10, 1, 1, None, 0, None) == -5
     assert lib.cgs2_orth(0, 10, 3, 1, 5, 1, 1, None, 0, None) == -1
     assert lib.cgs2_orth(0, 10, 3, 1, 10, 1, 1, None, 0, None) == -3
     assert lib.poly_prec_setup(C.byref(A), 129, 1, None, 0, C.byref(C.c_void_p()), None) == -5

@@ -111,7 +111,7 @@ def _basis(n, k, seed, dt):
     return Q.astype(dt)
 
 
-@pytest.mark.parametrize("k", [1, 5, 8, 9, 17, 33, 50, 64, 65, 100, 129, 200, 256])
+@pytest.mark.parametrize("k", [1, 5, 8, 9, 17, 33, 50, 64, 65, 100, 129, 200, 256, 257, 300, 512])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("aligned", [False, True])
 def test_cgs2_orth_matches_oracle(k, prec, aligned):
@@ -474,7 +474,7 @@ def test_persistent_cycle_small_laplacian_against_oracle():
     assert np.all(np.abs(np.log10(h[:k]) - np.log10(hr[:k])) < 1.0)
 
 
-@pytest.mark.parametrize("n_side,restart", [(17, 8), (30, 30), (32, 70)])
+@pytest.mark.parametrize("n_side,restart", [(17, 8), (30, 30), (32, 70), (24, 300)])
 def test_persistent_cycle_matches_multikernel(n_side, restart):
     # ragged last SpMV chunk, restart beyond the fused 64-column pass, the largest n (1024)
     say("persistent vs multi-kernel", n_side, restart)
