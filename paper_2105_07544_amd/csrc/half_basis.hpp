@@ -65,11 +65,13 @@ __global__ __launch_bounds__(kBlock) void hb_dots_kernel(int n, int j, const hal
     for (int i = 0; i < KO; ++i) acc[q][i] = 0.f;
   for (int grp = gw; grp < ngrp; grp += G) {
     const int r = grp * 2 * kWave + 2 * lane;
-    const bool full = r + 1 < n;
     const bool one = r < n;
+    const bool full = r + 1 < n;
+    // branch-free loads: row r + 1 of a basis column lies inside the column
+    // even past n (columns are padded to a multiple of 64 rows); the padding
+    // is never written, so its value is replaced by zero, as is w's
     fvec2_t wv = {0.f, 0.f};
-    if (full) wv = *reinterpret_cast<const fvec2_t*>(w + r);
-    else if (one) wv.x = w[r];
+    if (one) wv = fvec2_t{w[r], full ? w[r + 1] : 0.f};
     wv *= inv_sigma;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -79,11 +81,8 @@ __global__ __launch_bounds__(kBlock) void hb_dots_kernel(int n, int j, const hal
         for (int c = 0; c < K; ++c) {
           const int col = q * K + c;
           hvec2_t v = {half_t(0), half_t(0)};
-          if (col < j) {
-            const half_t* Vc = V + (size_t)col * ldv + r;
-            if (full) v = *reinterpret_cast<const hvec2_t*>(Vc);
-            else if (one) v.x = Vc[0];
-          }
+          if (col < j && one) v = *reinterpret_cast<const hvec2_t*>(V + (size_t)col * ldv + r);
+          if (!full) v.y = half_t(0);
           a[c] = float(v.x) * wv.x + float(v.y) * wv.y;
         }
         Butterfly<K>::run(a, lane);
@@ -118,19 +117,17 @@ __global__ __launch_bounds__(kBlock) void hb_update_dots_kernel(int n, int j, co
     const int r = grp * 2 * kWave + 2 * lane;
     const bool full = r + 1 < n;
     const bool one = r < n;
+    // branch-free loads as in the dots pass (the padding row's values become
+    // zero; its update is never stored)
     hvec2_t v[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       v[c] = hvec2_t{half_t(0), half_t(0)};
-      if (c < j) {
-        const half_t* Vc = V + (size_t)c * ldv + r;
-        if (full) v[c] = *reinterpret_cast<const hvec2_t*>(Vc);
-        else if (one) v[c].x = Vc[0];
-      }
+      if (c < j && one) v[c] = *reinterpret_cast<const hvec2_t*>(V + (size_t)c * ldv + r);
+      if (!full) v[c].y = half_t(0);
     }
     fvec2_t wv = {0.f, 0.f};
-    if (full) wv = *reinterpret_cast<const fvec2_t*>(w + r);
-    else if (one) wv.x = w[r];
+    if (one) wv = fvec2_t{w[r], full ? w[r + 1] : 0.f};
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       wv.x -= float(v[c].x) * s_h[c];

@@ -137,3 +137,20 @@ def test_half_basis_ignores_the_persistent_flag():
     x0, r0 = G.gmres_ir_solve(A64, A32, t64(b), restart=20, half_basis=True)
     x1, r1 = G.gmres_ir_solve(A64, A32, t64(b), restart=20, half_basis=True, persistent=True)
     assert r0.converged and r0.iters == r1.iters and np.array_equal(host(x0), host(x1))
+
+
+@pytest.mark.parametrize("fill", [0x00, 0xFF, 0x7C])
+def test_half_basis_poisoned_workspace_gives_identical_results(fill):
+    """Odd n: the float16 passes read the padding row of each basis column and must
+    not let its contents (never written; NaN or Inf patterns here) reach the result."""
+    A = W.laplace2d(37)   # n = 1369, odd
+    b = W.host_matvec(A, W.uniform_pm1(6, A.n))
+    A64 = G.DeviceCSR.from_host(A, DEV)
+    A32 = A64.to_f32()
+    ws = G.alloc_workspace(G.workspace_bytes(A.n, 30, G.GMR_F32), DEV)
+    ws.fill_(0)
+    x0, r0 = G.gmres_ir_solve(A64, A32, t64(b), restart=30, ws=ws, half_basis=True)
+    ws.fill_(fill)
+    x1, r1 = G.gmres_ir_solve(A64, A32, t64(b), restart=30, ws=ws, half_basis=True)
+    assert r0.converged and r1.converged and r0.iters == r1.iters
+    assert np.array_equal(host(x0), host(x1))
