@@ -15,7 +15,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gmres_ir.h"
@@ -57,6 +60,36 @@ static inline int dots_grid(int n) { return std::max(1, std::min(ceil_div(ceil_d
 static inline int dots4_grid(int n) { return dots_grid(ceil_div(n, 4)); }
 // Grid of the streaming kernels.
 static inline int stream_grid(int n) { return std::max(1, std::min(ceil_div(n, kBlock), kMaxRedBlocks)); }
+
+// Blocks of kBlock threads of `fn` that the current device holds at once
+// (occupancy per CU times the CU count), cached per device and kernel.
+static int resident_blocks(const void* fn) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return kMaxRedBlocks;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(dev, fn);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  int v = kMaxRedBlocks;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0 &&
+      cus > 0)
+    v = per_cu * cus;
+  cache[key] = v;
+  return v;
+}
+
+// A grid-stride grid of at most `want` blocks cut to a whole number of
+// resident rounds: with 144 VGPRs (three waves per SIMD, 768 blocks on 256
+// CUs) a 1024-block grid would leave its last 256 blocks to run alone on a
+// mostly idle chip.
+static int balanced_grid(int want, const void* fn) {
+  const int res = resident_blocks(fn);
+  return want <= res ? want : (want / res) * res;
+}
 
 // ---------------------------------------------------------------------------
 // Workspace.  A fixed "small" region (reduction partials, the
@@ -295,9 +328,13 @@ static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t l
     return launch_dots<T>(c, n, j, V, ldv, w, ws, hd, ht, done);
   }
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
-  const int G = dots_grid(n);
+  int G = dots_grid(n);
   double* part = ws.partial();
-#define GMR_UD(K) cgs_update_dots_kernel<T, K><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, part, done)
+#define GMR_UD(K)                                                                        \
+  do {                                                                                   \
+    G = balanced_grid(G, reinterpret_cast<const void*>(cgs_update_dots_kernel<T, K>));   \
+    cgs_update_dots_kernel<T, K><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, part, done); \
+  } while (0)
   if (j <= 8) GMR_UD(8);
   else if (j <= 16) GMR_UD(16);
   else if (j <= 32) GMR_UD(32);
@@ -353,6 +390,7 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
   GMR_TRY(check_launch("finish_cols_kernel"));
   // pass-1 update and pass-2 dots
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
+  int GU = G;   // the grid whose partials the second finish_cols reads
   if (j > 64) {
     hb_update_kernel<false><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w,
                                                                part, done);
@@ -362,8 +400,11 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
     else GMR_HD(64, 8);
     GMR_TRY(check_launch("hb_dots_kernel"));
   } else {
-#define GMR_HUD(K) \
-  hb_update_dots_kernel<K><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w, part, done)
+#define GMR_HUD(K)                                                                                         \
+  do {                                                                                                     \
+    GU = balanced_grid(G, reinterpret_cast<const void*>(hb_update_dots_kernel<K>));                          \
+    hb_update_dots_kernel<K><<<GU, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w, part, done); \
+  } while (0)
     if (j <= 8) GMR_HUD(8);
     else if (j <= 16) GMR_HUD(16);
     else if (j <= 32) GMR_HUD(32);
@@ -373,7 +414,7 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
     GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, vb + 8.0 * n));
   }
 #undef GMR_HD
-  finish_cols_kernel<float><<<j, kBlock, 0, c.s>>>(G, part, cs.h2d, ws.h2t<float>(), done);
+  finish_cols_kernel<float><<<j, kBlock, 0, c.s>>>(GU, part, cs.h2d, ws.h2t<float>(), done);
   GMR_TRY(check_launch("finish_cols_kernel"));
   // pass-2 update, norm, Givens
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_NORM));
