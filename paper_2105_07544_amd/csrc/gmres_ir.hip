@@ -291,19 +291,22 @@ static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, con
     finish_cols_kernel<T><<<j, kBlock, 0, c.s>>>(G, part, hd, ht, done);
     return check_launch("finish_cols_kernel");
   }
-  const int G = dots4_grid(n);
-  if (j <= 8)
-    cgs_dots4_kernel<T, 8, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
-  else if (j <= 16)
-    cgs_dots4_kernel<T, 16, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
-  else if (j <= 32)
-    cgs_dots4_kernel<T, 32, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
-  else if (j <= 64)
-    cgs_dots4_kernel<T, 64, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
-  else if (j <= 256)
-    cgs_dots4_kernel<T, 64, 4><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
-  else
-    cgs_dots4_kernel<T, 64, 8><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+  // Beyond 32 columns the basis is read in 32-column chunks: a 64-column chunk
+  // of four rows per lane keeps 256 VGPRs live and runs one wave per SIMD.
+  int G = dots4_grid(n);
+#define GMR_D4(K, NQ)                                                                   \
+  do {                                                                                  \
+    G = balanced_grid(G, reinterpret_cast<const void*>(cgs_dots4_kernel<T, K, NQ>));     \
+    cgs_dots4_kernel<T, K, NQ><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);      \
+  } while (0)
+  if (j <= 8) GMR_D4(8, 1);
+  else if (j <= 16) GMR_D4(16, 1);
+  else if (j <= 32) GMR_D4(32, 1);
+  else if (j <= 64) GMR_D4(32, 2);
+  else if (j <= 128) GMR_D4(32, 4);
+  else if (j <= 256) GMR_D4(32, 8);
+  else GMR_D4(32, 16);
+#undef GMR_D4
   GMR_TRY(check_launch("cgs_dots_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_DOTS, (double)(j + 1) * n * sizeof(T)));
   finish_cols_kernel<T><<<j, kBlock, 0, c.s>>>(G, part, hd, ht, done);
