@@ -325,7 +325,8 @@ static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t l
   if (j > fused_max<T>()) {
     // no room to keep the row in registers: update, then a separate dots pass
     GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
-    cgs_update_kernel<T><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, done);
+    // descending rows: the dots pass before ends on the highest rows
+    cgs_update_kernel<T><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, done, 1);
     GMR_TRY(check_launch("cgs_update_kernel"));
     GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, (double)(j + 2) * n * sizeof(T)));
     return launch_dots<T>(c, n, j, V, ldv, w, ws, hd, ht, done);
@@ -356,7 +357,12 @@ static gmr_status launch_update_norm(Ctx& c, int n, int j, const T* V, int64_t l
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_NORM));
   const double thresh = sizeof(T) == 4 ? 1e3 * 1.1754943508222875e-38 : 0.0;
   const int G = stream_grid(n);
-  cgs_update_norm_kernel<T><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, ws.partial(), done);
+  // Start on the rows the previous pass over V ended on, which the
+  // memory-side cache still holds: after the fused update+dots (downward)
+  // run upward; beyond fused_max the previous pass is the separate dots
+  // pass (upward), so run downward.
+  const int rev = j > fused_max<T>() ? 1 : 0;
+  cgs_update_norm_kernel<T><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, ws.partial(), done, rev);
   GMR_TRY(check_launch("cgs_update_norm_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_NORM, (double)(j + 2) * n * sizeof(T)));
   finish_norm_kernel<T, MODE><<<1, kBlock, 0, c.s>>>(G, ws.partial(), cs, j, last_jc, thresh, hout, done);
@@ -396,7 +402,7 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
   int GU = G;   // the grid whose partials the second finish_cols reads
   if (j > 64) {
     hb_update_kernel<false><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w,
-                                                               part, done);
+                                                               part, done, 1);
     GMR_TRY(check_launch("hb_update_kernel"));
     GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, vb + 8.0 * n));
     if (j <= 256) GMR_HD(64, 4);
@@ -422,7 +428,8 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
   // pass-2 update, norm, Givens
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_NORM));
   const int GS = stream_grid(n);
-  hb_update_kernel<true><<<GS, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h2t<float>(), inv_sigma, w, part, done);
+  hb_update_kernel<true><<<GS, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h2t<float>(), inv_sigma, w, part, done,
+                                                 j > 64 ? 1 : 0);
   GMR_TRY(check_launch("hb_update_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_NORM, vb + 8.0 * n));
   finish_norm_kernel<float, kTailGivens><<<1, kBlock, 0, c.s>>>(GS, part, cs, j, last_jc, 1e3 * 1.1754943508222875e-38,

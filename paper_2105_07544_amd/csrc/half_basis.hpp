@@ -113,7 +113,9 @@ __global__ __launch_bounds__(kBlock) void hb_update_dots_kernel(int n, int j, co
   float acc[1][KO];
 #pragma unroll
   for (int i = 0; i < KO; ++i) acc[0][i] = 0.f;
-  for (int grp = gw; grp < ngrp; grp += G) {
+  // descending row groups, as in the float32 kernel (memory-side cache reuse)
+  for (int it = gw; it < ngrp; it += G) {
+    const int grp = ngrp - 1 - it;
     const int r = grp * 2 * kWave + 2 * lane;
     const bool full = r + 1 < n;
     const bool one = r < n;
@@ -199,11 +201,13 @@ __device__ __forceinline__ float hb_update_row(int j, const half_t* __restrict__
 }
 
 // w -= V_j h_in; with NORM, also the block's partial ||w||^2 in partial[blockIdx.x].
+// With rev the row quads are taken in descending order.
 template <bool NORM>
 __global__ __launch_bounds__(kBlock) void hb_update_kernel(int n, int j, const half_t* __restrict__ V,
                                                            int64_t ldv, const float* __restrict__ h_in,
                                                            float inv_sigma, float* __restrict__ w,
-                                                           double* partial, const int* __restrict__ done) {
+                                                           double* partial, const int* __restrict__ done,
+                                                           int rev) {
   __shared__ float s_h[kMaxCols];
   if (done && *done) return;
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c] * inv_sigma;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void hb_update_kernel(int n, int j, const h
   const int nq = n / 4;
   float o[4];
   for (int q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
-    hb_update_rows4(j, V, ldv, s_h, w, 4 * q, o);
+    hb_update_rows4(j, V, ldv, s_h, w, 4 * (rev ? nq - 1 - q : q), o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) sq += o[i] * o[i];
   }

@@ -488,7 +488,11 @@ __device__ __forceinline__ void cgs_update_dots_body(
   T acc[1][KO];
 #pragma unroll
   for (int i = 0; i < KO; ++i) acc[0][i] = T(0);
-  for (int grp = gw; grp < ngrp; grp += G) {
+  // Row groups in descending order: the dots pass before this one streams V
+  // upward, so its last rows are the ones still in the memory-side cache, and
+  // the update+norm pass after this one starts from the rows this one ends on.
+  for (int it = gw; it < ngrp; it += G) {
+    const int grp = ngrp - 1 - it;
     const int r = grp * kWave + lane;
     const bool ok = r < n;
     T v[K];
@@ -564,7 +568,7 @@ template <class T>
 __device__ __forceinline__ void cgs_update_body(int n, int j, const T* __restrict__ V,
                                                 int64_t ldv, const T* __restrict__ h_in,
                                                 T* __restrict__ w,
-                                                const int* __restrict__ done) {
+                                                const int* __restrict__ done, bool rev = false) {
   __shared__ T s_h[kMaxCols];
   if (done && *done) return;
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
@@ -572,7 +576,7 @@ __device__ __forceinline__ void cgs_update_body(int n, int j, const T* __restric
   const int nq = rows4_ok(V, ldv, w) ? n / 4 : 0;
   T o[4];
   for (int q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock)
-    update_rows4<T>(j, V, ldv, s_h, w, 4 * q, o);
+    update_rows4<T>(j, V, ldv, s_h, w, 4 * (rev ? nq - 1 - q : q), o);
   for (int r = 4 * nq + blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock)
     update_row<T>(j, V, ldv, s_h, w, r);
 }
@@ -581,8 +585,8 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void cgs_update_kernel(int n, int j, const T* __restrict__ V,
                                                             int64_t ldv, const T* __restrict__ h_in,
                                                             T* __restrict__ w,
-                                                            const int* __restrict__ done) {
-  cgs_update_body<T>(n, j, V, ldv, h_in, w, done);
+                                                            const int* __restrict__ done, int rev) {
+  cgs_update_body<T>(n, j, V, ldv, h_in, w, done, rev != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -684,10 +688,12 @@ __device__ __forceinline__ void givens_tail(CycleState cs, int jc, int last_jc, 
 
 // Pass-2 update and norm: w -= V_j h_in with the block's partial ||w||^2
 // accumulated in the working precision; four rows per thread at a time.
+// With rev the row quads are taken in descending order (so that the pass
+// starts on the rows the previous pass over V ended on).
 template <class T>
 __device__ __forceinline__ void cgs_update_norm_body(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
-    T* __restrict__ w, double* partial, const int* __restrict__ done) {
+    T* __restrict__ w, double* partial, const int* __restrict__ done, bool rev = false) {
   __shared__ T s_h[kMaxCols];
   if (done && *done) return;
   for (int c = threadIdx.x; c < j; c += kBlock) s_h[c] = h_in[c];
@@ -696,7 +702,7 @@ __device__ __forceinline__ void cgs_update_norm_body(
   const int nq = rows4_ok(V, ldv, w) ? n / 4 : 0;
   T o[4];
   for (int q = blockIdx.x * kBlock + threadIdx.x; q < nq; q += gridDim.x * kBlock) {
-    update_rows4<T>(j, V, ldv, s_h, w, 4 * q, o);
+    update_rows4<T>(j, V, ldv, s_h, w, 4 * (rev ? nq - 1 - q : q), o);
 #pragma unroll
     for (int i = 0; i < 4; ++i) sq += o[i] * o[i];
   }
@@ -711,8 +717,8 @@ __device__ __forceinline__ void cgs_update_norm_body(
 template <class T>
 __global__ __launch_bounds__(kBlock) void cgs_update_norm_kernel(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
-    T* __restrict__ w, double* partial, const int* __restrict__ done) {
-  cgs_update_norm_body<T>(n, j, V, ldv, h_in, w, partial, done);
+    T* __restrict__ w, double* partial, const int* __restrict__ done, int rev) {
+  cgs_update_norm_body<T>(n, j, V, ldv, h_in, w, partial, done, rev != 0);
 }
 
 // beta = ||w|| from the partials, then the tail: the Givens step (solver) or
