@@ -264,7 +264,7 @@ static gmr_status launch_spmv(Ctx& c, const gmr_csr* A, const T* x, const double
 
 template <class T>
 static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* w,
-                              const Ws& ws, double* hd, T* ht, const int* done) {
+                              const Ws& ws, double* hd, T* ht, const int* done, int rev) {
   GMR_TRY(c.begin(GMR_PROF_CGS_DOTS));
   double* part = ws.partial();
   // four rows per lane in float32 when the basis is vector-aligned (measured on
@@ -275,17 +275,17 @@ static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, con
   if (!rows4) {
     const int G = dots_grid(n);
     if (j <= 8)
-      cgs_dots_kernel<T, 8, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+      cgs_dots_kernel<T, 8, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done, rev);
     else if (j <= 16)
-      cgs_dots_kernel<T, 16, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+      cgs_dots_kernel<T, 16, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done, rev);
     else if (j <= 32)
-      cgs_dots_kernel<T, 32, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+      cgs_dots_kernel<T, 32, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done, rev);
     else if (j <= 64)
-      cgs_dots_kernel<T, 64, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+      cgs_dots_kernel<T, 64, 1><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done, rev);
     else if (j <= 256)
-      cgs_dots_kernel<T, 64, 4><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+      cgs_dots_kernel<T, 64, 4><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done, rev);
     else
-      cgs_dots_kernel<T, 64, 8><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);
+      cgs_dots_kernel<T, 64, 8><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done, rev);
     GMR_TRY(check_launch("cgs_dots_kernel"));
     GMR_TRY(c.end(GMR_PROF_CGS_DOTS, (double)(j + 1) * n * sizeof(T)));
     finish_cols_kernel<T><<<j, kBlock, 0, c.s>>>(G, part, hd, ht, done);
@@ -297,7 +297,7 @@ static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, con
 #define GMR_D4(K, NQ)                                                                   \
   do {                                                                                  \
     G = balanced_grid(G, reinterpret_cast<const void*>(cgs_dots4_kernel<T, K, NQ>));     \
-    cgs_dots4_kernel<T, K, NQ><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done);      \
+    cgs_dots4_kernel<T, K, NQ><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, part, done, rev); \
   } while (0)
   if (j <= 8) GMR_D4(8, 1);
   else if (j <= 16) GMR_D4(16, 1);
@@ -321,15 +321,14 @@ template <class T> constexpr int fused_max() { return 64; }
 
 template <class T>
 static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* hin,
-                                     T* w, const Ws& ws, double* hd, T* ht, const int* done) {
+                                     T* w, const Ws& ws, double* hd, T* ht, const int* done, int rev) {
   if (j > fused_max<T>()) {
     // no room to keep the row in registers: update, then a separate dots pass
     GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
-    // descending rows: the dots pass before ends on the highest rows
-    cgs_update_kernel<T><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, done, 1);
+    cgs_update_kernel<T><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, done, rev);
     GMR_TRY(check_launch("cgs_update_kernel"));
     GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, (double)(j + 2) * n * sizeof(T)));
-    return launch_dots<T>(c, n, j, V, ldv, w, ws, hd, ht, done);
+    return launch_dots<T>(c, n, j, V, ldv, w, ws, hd, ht, done, !rev);
   }
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_DOTS));
   int G = dots_grid(n);
@@ -337,7 +336,7 @@ static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t l
 #define GMR_UD(K)                                                                        \
   do {                                                                                   \
     G = balanced_grid(G, reinterpret_cast<const void*>(cgs_update_dots_kernel<T, K>));   \
-    cgs_update_dots_kernel<T, K><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, part, done); \
+    cgs_update_dots_kernel<T, K><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, part, done, rev); \
   } while (0)
   if (j <= 8) GMR_UD(8);
   else if (j <= 16) GMR_UD(16);
@@ -353,15 +352,10 @@ static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t l
 template <class T, int MODE>
 static gmr_status launch_update_norm(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* hin,
                                      T* w, const Ws& ws, CycleState cs, int last_jc,
-                                     double* hout, const int* done) {
+                                     double* hout, const int* done, int rev) {
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_NORM));
   const double thresh = sizeof(T) == 4 ? 1e3 * 1.1754943508222875e-38 : 0.0;
   const int G = stream_grid(n);
-  // Start on the rows the previous pass over V ended on, which the
-  // memory-side cache still holds: after the fused update+dots (downward)
-  // run upward; beyond fused_max the previous pass is the separate dots
-  // pass (upward), so run downward.
-  const int rev = j > fused_max<T>() ? 1 : 0;
   cgs_update_norm_kernel<T><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, hin, w, ws.partial(), done, rev);
   GMR_TRY(check_launch("cgs_update_norm_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_NORM, (double)(j + 2) * n * sizeof(T)));
@@ -369,13 +363,22 @@ static gmr_status launch_update_norm(Ctx& c, int n, int j, const T* V, int64_t l
   return check_launch("finish_norm_kernel");
 }
 
+// Direction of the first pass over V at basis size j.  Each pass runs
+// opposite to the one before it, so that it starts on the rows the
+// memory-side cache still holds.  With the fused update+dots an iteration
+// makes three passes (odd), so the first direction flips with j; with the
+// separate update and dots it makes four, and the direction stays fixed.
+static inline int first_pass_rev(int j, int fused) { return j > fused ? 1 : (j & 1); }
+
 // The three CGS2 passes on w against V[:, 0:j].
 template <class T, int MODE>
 static gmr_status cgs2_passes(Ctx& c, int n, int j, const T* V, int64_t ldv, T* w, const Ws& ws,
                               CycleState cs, int last_jc, double* hout, const int* done) {
-  GMR_TRY(launch_dots<T>(c, n, j, V, ldv, w, ws, cs.h1d, ws.h1t<T>(), done));
-  GMR_TRY(launch_update_dots<T>(c, n, j, V, ldv, ws.h1t<T>(), w, ws, cs.h2d, ws.h2t<T>(), done));
-  return launch_update_norm<T, MODE>(c, n, j, V, ldv, ws.h2t<T>(), w, ws, cs, last_jc, hout, done);
+  const int rev = first_pass_rev(j, fused_max<T>());
+  const int last = j > fused_max<T>() ? !rev : rev;
+  GMR_TRY(launch_dots<T>(c, n, j, V, ldv, w, ws, cs.h1d, ws.h1t<T>(), done, rev));
+  GMR_TRY(launch_update_dots<T>(c, n, j, V, ldv, ws.h1t<T>(), w, ws, cs.h2d, ws.h2t<T>(), done, !rev));
+  return launch_update_norm<T, MODE>(c, n, j, V, ldv, ws.h2t<T>(), w, ws, cs, last_jc, hout, done, last);
 }
 
 // The three CGS2 passes with the basis stored in float16 (scaled by sigma).
@@ -383,16 +386,17 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
                                  CycleState cs, int last_jc, float inv_sigma, const int* done) {
   double* part = ws.partial();
   const double vb = (double)j * n * sizeof(half_t);
+  const int rev = first_pass_rev(j, 64);   // the pass order of the float32 path
   // pass 1: h1 = V^T w
   GMR_TRY(c.begin(GMR_PROF_CGS_DOTS));
   const int G = dots_grid(ceil_div(n, 2));
-#define GMR_HD(K, NQ) hb_dots_kernel<K, NQ><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, inv_sigma, part, done)
-  if (j <= 8) GMR_HD(8, 1);
-  else if (j <= 16) GMR_HD(16, 1);
-  else if (j <= 32) GMR_HD(32, 1);
-  else if (j <= 64) GMR_HD(64, 1);
-  else if (j <= 256) GMR_HD(64, 4);
-  else GMR_HD(64, 8);
+#define GMR_HD(K, NQ, R) hb_dots_kernel<K, NQ><<<G, kBlock, 0, c.s>>>(n, j, V, ldv, w, inv_sigma, part, done, R)
+  if (j <= 8) GMR_HD(8, 1, rev);
+  else if (j <= 16) GMR_HD(16, 1, rev);
+  else if (j <= 32) GMR_HD(32, 1, rev);
+  else if (j <= 64) GMR_HD(64, 1, rev);
+  else if (j <= 256) GMR_HD(64, 4, rev);
+  else GMR_HD(64, 8, rev);
   GMR_TRY(check_launch("hb_dots_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_DOTS, vb + 4.0 * n));
   finish_cols_kernel<float><<<j, kBlock, 0, c.s>>>(G, part, cs.h1d, ws.h1t<float>(), done);
@@ -402,17 +406,18 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
   int GU = G;   // the grid whose partials the second finish_cols reads
   if (j > 64) {
     hb_update_kernel<false><<<stream_grid(n), kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w,
-                                                               part, done, 1);
+                                                               part, done, !rev);
     GMR_TRY(check_launch("hb_update_kernel"));
     GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, vb + 8.0 * n));
-    if (j <= 256) GMR_HD(64, 4);
-    else GMR_HD(64, 8);
+    if (j <= 256) GMR_HD(64, 4, rev);
+    else GMR_HD(64, 8, rev);
     GMR_TRY(check_launch("hb_dots_kernel"));
   } else {
 #define GMR_HUD(K)                                                                                         \
   do {                                                                                                     \
     GU = balanced_grid(G, reinterpret_cast<const void*>(hb_update_dots_kernel<K>));                          \
-    hb_update_dots_kernel<K><<<GU, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w, part, done); \
+    hb_update_dots_kernel<K><<<GU, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h1t<float>(), inv_sigma, w, part, done, \
+                                                     !rev);                                                  \
   } while (0)
     if (j <= 8) GMR_HUD(8);
     else if (j <= 16) GMR_HUD(16);
@@ -429,7 +434,7 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
   GMR_TRY(c.begin(GMR_PROF_CGS_UPDATE_NORM));
   const int GS = stream_grid(n);
   hb_update_kernel<true><<<GS, kBlock, 0, c.s>>>(n, j, V, ldv, ws.h2t<float>(), inv_sigma, w, part, done,
-                                                 j > 64 ? 1 : 0);
+                                                 j > 64 ? !rev : rev);
   GMR_TRY(check_launch("hb_update_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_NORM, vb + 8.0 * n));
   finish_norm_kernel<float, kTailGivens><<<1, kBlock, 0, c.s>>>(GS, part, cs, j, last_jc, 1e3 * 1.1754943508222875e-38,

@@ -51,7 +51,7 @@ template <int K, int NQ>
 __global__ __launch_bounds__(kBlock) void hb_dots_kernel(int n, int j, const half_t* __restrict__ V,
                                                          int64_t ldv, const float* __restrict__ w,
                                                          float inv_sigma, double* partial,
-                                                         const int* __restrict__ done) {
+                                                         const int* __restrict__ done, int rev) {
   constexpr int KO = Butterfly<K>::KOut;
   if (done && *done) return;
   const int lane = threadIdx.x % kWave;
@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kBlock) void hb_dots_kernel(int n, int j, const hal
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int i = 0; i < KO; ++i) acc[q][i] = 0.f;
-  for (int grp = gw; grp < ngrp; grp += G) {
+  for (int it = gw; it < ngrp; it += G) {
+    const int grp = rev ? ngrp - 1 - it : it;
     const int r = grp * 2 * kWave + 2 * lane;
     const bool one = r < n;
     const bool full = r + 1 < n;
@@ -100,7 +101,8 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void hb_update_dots_kernel(int n, int j, const half_t* __restrict__ V,
                                                                 int64_t ldv, const float* __restrict__ h_in,
                                                                 float inv_sigma, float* __restrict__ w,
-                                                                double* partial, const int* __restrict__ done) {
+                                                                double* partial, const int* __restrict__ done,
+                                                                int rev) {
   constexpr int KO = Butterfly<K>::KOut;
   __shared__ float s_h[K];
   if (done && *done) return;
@@ -113,9 +115,9 @@ __global__ __launch_bounds__(kBlock) void hb_update_dots_kernel(int n, int j, co
   float acc[1][KO];
 #pragma unroll
   for (int i = 0; i < KO; ++i) acc[0][i] = 0.f;
-  // descending row groups, as in the float32 kernel (memory-side cache reuse)
+  // rev: descending row groups, as in the float32 kernels
   for (int it = gw; it < ngrp; it += G) {
-    const int grp = ngrp - 1 - it;
+    const int grp = rev ? ngrp - 1 - it : it;
     const int r = grp * 2 * kWave + 2 * lane;
     const bool full = r + 1 < n;
     const bool one = r < n;

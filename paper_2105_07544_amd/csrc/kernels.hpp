@@ -354,12 +354,20 @@ __global__ __launch_bounds__(kBlock) void finish_cols_kernel(int nparts, const d
   }
 }
 
+// Pass order.  The memory-side cache keeps the rows of V that a pass touched
+// last.  Every pass over V takes a direction flag `rev` (row groups in
+// descending order), and the host alternates it so that each pass starts on
+// the rows the pass before it ended on: a basis larger than the cache then
+// still finds about a cache's worth of it there, where passes that all ran
+// upward would each evict what the next one needs first.  The order of the
+// rows changes only which rows a block sums, not what is computed.
+
 // Pass 1: h = V_j^T w  (j <= NQ * K columns, in NQ chunks of K columns).
 template <class T, int K, int NQ>
 __device__ __forceinline__ void cgs_dots_body(int n, int j, const T* __restrict__ V,
                                               int64_t ldv, const T* __restrict__ w,
                                               double* partial,
-                                              const int* __restrict__ done) {
+                                              const int* __restrict__ done, bool rev = false) {
   constexpr int KO = Butterfly<K>::KOut;
   if (done && *done) return;
   const int lane = threadIdx.x % kWave;
@@ -371,7 +379,8 @@ __device__ __forceinline__ void cgs_dots_body(int n, int j, const T* __restrict_
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int i = 0; i < KO; ++i) acc[q][i] = T(0);
-  for (int grp = gw; grp < ngrp; grp += G) {
+  for (int it = gw; it < ngrp; it += G) {
+    const int grp = rev ? ngrp - 1 - it : it;
     const int r = grp * kWave + lane;
     const bool ok = r < n;
     const T wv = ok ? w[r] : T(0);
@@ -402,7 +411,7 @@ __device__ __forceinline__ void cgs_dots_body(int n, int j, const T* __restrict_
 template <class T, int K, int NQ>
 __device__ __forceinline__ void cgs_dots4_body(int n, int j, const T* __restrict__ V, int64_t ldv,
                                                const T* __restrict__ w, double* partial,
-                                               const int* __restrict__ done) {
+                                               const int* __restrict__ done, bool rev = false) {
   typedef T v4 __attribute__((ext_vector_type(4)));
   constexpr int KO = Butterfly<K>::KOut;
   if (done && *done) return;
@@ -415,7 +424,8 @@ __device__ __forceinline__ void cgs_dots4_body(int n, int j, const T* __restrict
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int i = 0; i < KO; ++i) acc[q][i] = T(0);
-  for (int grp = gw; grp < ngrp; grp += G) {
+  for (int it = gw; it < ngrp; it += G) {
+    const int grp = rev ? ngrp - 1 - it : it;
     const int r = grp * 4 * kWave + 4 * lane;
     const bool full = r + 3 < n;
     v4 wv;
@@ -457,16 +467,16 @@ template <class T, int K, int NQ>
 __global__ __launch_bounds__(kBlock) void cgs_dots4_kernel(int n, int j, const T* __restrict__ V,
                                                            int64_t ldv, const T* __restrict__ w,
                                                            double* partial,
-                                                           const int* __restrict__ done) {
-  cgs_dots4_body<T, K, NQ>(n, j, V, ldv, w, partial, done);
+                                                           const int* __restrict__ done, int rev) {
+  cgs_dots4_body<T, K, NQ>(n, j, V, ldv, w, partial, done, rev != 0);
 }
 
 template <class T, int K, int NQ>
 __global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T* __restrict__ V,
                                                           int64_t ldv, const T* __restrict__ w,
                                                           double* partial,
-                                                          const int* __restrict__ done) {
-  cgs_dots_body<T, K, NQ>(n, j, V, ldv, w, partial, done);
+                                                          const int* __restrict__ done, int rev) {
+  cgs_dots_body<T, K, NQ>(n, j, V, ldv, w, partial, done, rev != 0);
 }
 
 // Pass-1 update fused with pass-2 dots: w -= V_j h_in ; h_out = V_j^T w.
@@ -475,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T*
 template <class T, int K>
 __device__ __forceinline__ void cgs_update_dots_body(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
-    T* __restrict__ w, double* partial, const int* __restrict__ done) {
+    T* __restrict__ w, double* partial, const int* __restrict__ done, bool rev = false) {
   constexpr int KO = Butterfly<K>::KOut;
   __shared__ T s_h[K];
   if (done && *done) return;
@@ -488,11 +498,9 @@ __device__ __forceinline__ void cgs_update_dots_body(
   T acc[1][KO];
 #pragma unroll
   for (int i = 0; i < KO; ++i) acc[0][i] = T(0);
-  // Row groups in descending order: the dots pass before this one streams V
-  // upward, so its last rows are the ones still in the memory-side cache, and
-  // the update+norm pass after this one starts from the rows this one ends on.
+  // rev: row groups in descending order (see the pass-order note above)
   for (int it = gw; it < ngrp; it += G) {
-    const int grp = ngrp - 1 - it;
+    const int grp = rev ? ngrp - 1 - it : it;
     const int r = grp * kWave + lane;
     const bool ok = r < n;
     T v[K];
@@ -514,8 +522,8 @@ __device__ __forceinline__ void cgs_update_dots_body(
 template <class T, int K>
 __global__ __launch_bounds__(kBlock) void cgs_update_dots_kernel(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
-    T* __restrict__ w, double* partial, const int* __restrict__ done) {
-  cgs_update_dots_body<T, K>(n, j, V, ldv, h_in, w, partial, done);
+    T* __restrict__ w, double* partial, const int* __restrict__ done, int rev) {
+  cgs_update_dots_body<T, K>(n, j, V, ldv, h_in, w, partial, done, rev != 0);
 }
 
 // w[r..r+3] -= sum_c V[c][r..r+3] h[c] over the j columns in ascending c: the
