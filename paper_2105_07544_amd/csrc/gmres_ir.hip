@@ -314,10 +314,11 @@ static gmr_status launch_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, con
 }
 
 // Largest j for which the update and the second dots fuse (basis row in
-// registers).  Beyond 64 columns the register footprint drops the fused
-// kernel to one wave per SIMD, and the separate update and dots passes are
-// faster although they read V twice.
-template <class T> constexpr int fused_max() { return 64; }
+// registers).  float32: 128 columns in 151 VGPRs (three waves per SIMD, with
+// the coefficients in scalar registers).  float64: beyond 64 columns the
+// fused kernel would run one wave per SIMD, and the separate update and dots
+// passes are faster although they read V twice.
+template <class T> constexpr int fused_max() { return sizeof(T) == 4 ? 128 : 64; }
 
 template <class T>
 static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t ldv, const T* hin,
@@ -341,7 +342,8 @@ static gmr_status launch_update_dots(Ctx& c, int n, int j, const T* V, int64_t l
   if (j <= 8) GMR_UD(8);
   else if (j <= 16) GMR_UD(16);
   else if (j <= 32) GMR_UD(32);
-  else GMR_UD(64);
+  else if (j <= 64) GMR_UD(64);
+  else if constexpr (sizeof(T) == 4) GMR_UD(128);
 #undef GMR_UD
   GMR_TRY(check_launch("cgs_update_dots_kernel"));
   GMR_TRY(c.end(GMR_PROF_CGS_UPDATE_DOTS, (double)(j + 2) * n * sizeof(T)));
@@ -386,7 +388,7 @@ static gmr_status hb_cgs2_passes(Ctx& c, int n, int j, const half_t* V, int64_t 
                                  CycleState cs, int last_jc, float inv_sigma, const int* done) {
   double* part = ws.partial();
   const double vb = (double)j * n * sizeof(half_t);
-  const int rev = first_pass_rev(j, 64);   // the pass order of the float32 path
+  const int rev = first_pass_rev(j, 64);   // same rule; the fused kernel here takes up to 64 columns
   // pass 1: h1 = V^T w
   GMR_TRY(c.begin(GMR_PROF_CGS_DOTS));
   const int G = dots_grid(ceil_div(n, 2));

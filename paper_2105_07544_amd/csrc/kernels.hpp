@@ -482,22 +482,43 @@ __global__ __launch_bounds__(kBlock) void cgs_dots_kernel(int n, int j, const T*
 // Pass-1 update fused with pass-2 dots: w -= V_j h_in ; h_out = V_j^T w.
 // The j basis entries of a row stay in registers between the two uses, so V
 // is read once.  Needs j <= K.
-template <class T, int K>
+// STANDALONE (the kernel below, not the single-block cycle) selects two
+// register-saving forms where they pay:
+//  * float64, and float32 beyond 64 columns, read the coefficients with
+//    wave-uniform loads, which keeps them in scalar registers across the
+//    row-group loop; staged in LDS they are hoisted into K vector registers
+//    (float64, K = 64: 256 VGPRs -> 149; float32, K = 128: 151).  For
+//    float32 up to 64 columns the LDS form measured faster (5.64 against
+//    5.50 TB/s at K = 64 on a 3.4M-row basis);
+//  * float64 reduces the dots of more than 32 columns in 32-column chunks
+//    (149 VGPRs at K = 64 against 187).
+template <class T, int K, bool STANDALONE = false>
 __device__ __forceinline__ void cgs_update_dots_body(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
     T* __restrict__ w, double* partial, const int* __restrict__ done, bool rev = false) {
-  constexpr int KO = Butterfly<K>::KOut;
-  __shared__ T s_h[K];
+  constexpr bool kScalarH = STANDALONE && (sizeof(T) == 8 || K > 64);
+  constexpr int KC = (STANDALONE && K > 32 && sizeof(T) == 8) ? 32 : K;
+  constexpr int NQ = K / KC;
+  constexpr int KO = Butterfly<KC>::KOut;
+  __shared__ T s_h[kScalarH ? 1 : K];
   if (done && *done) return;
-  for (int c = threadIdx.x; c < K; c += kBlock) s_h[c] = (c < j) ? h_in[c] : T(0);
-  __syncthreads();
+  T hc[kScalarH ? K : 1];
+  if constexpr (kScalarH) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) hc[c] = (c < j) ? h_in[c] : T(0);
+  } else {
+    for (int c = threadIdx.x; c < K; c += kBlock) s_h[c] = (c < j) ? h_in[c] : T(0);
+    __syncthreads();
+  }
   const int lane = threadIdx.x % kWave;
   const int gw = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   const int G = gridDim.x * kWavesPerBlock;
   const int ngrp = (n + kWave - 1) / kWave;
-  T acc[1][KO];
+  T acc[NQ][KO];
 #pragma unroll
-  for (int i = 0; i < KO; ++i) acc[0][i] = T(0);
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int i = 0; i < KO; ++i) acc[q][i] = T(0);
   // rev: row groups in descending order (see the pass-order note above)
   for (int it = gw; it < ngrp; it += G) {
     const int grp = rev ? ngrp - 1 - it : it;
@@ -508,22 +529,28 @@ __device__ __forceinline__ void cgs_update_dots_body(
     for (int c = 0; c < K; ++c) v[c] = (c < j && ok) ? V[(size_t)c * ldv + r] : T(0);
     T wv = ok ? w[r] : T(0);
 #pragma unroll
-    for (int c = 0; c < K; ++c) wv -= v[c] * s_h[c];
+    for (int c = 0; c < K; ++c) wv -= v[c] * (kScalarH ? hc[c] : s_h[c]);
     if (ok) w[r] = wv;
+    // the dots in chunks of KC columns: a chunk's butterfly needs half as
+    // many received values live as one over all K columns
 #pragma unroll
-    for (int c = 0; c < K; ++c) v[c] *= wv;
-    Butterfly<K>::run(v, lane);
+    for (int q = 0; q < NQ; ++q) {
+      T a[KC];
 #pragma unroll
-    for (int i = 0; i < KO; ++i) acc[0][i] += v[i];
+      for (int c = 0; c < KC; ++c) a[c] = v[q * KC + c] * wv;
+      Butterfly<KC>::run(a, lane);
+#pragma unroll
+      for (int i = 0; i < KO; ++i) acc[q][i] += a[i];
+    }
   }
-  publish_col_partials<K, T, 1>(acc, j, partial);
+  publish_col_partials<KC, T, NQ>(acc, j, partial);
 }
 
 template <class T, int K>
 __global__ __launch_bounds__(kBlock) void cgs_update_dots_kernel(
     int n, int j, const T* __restrict__ V, int64_t ldv, const T* __restrict__ h_in,
     T* __restrict__ w, double* partial, const int* __restrict__ done, int rev) {
-  cgs_update_dots_body<T, K>(n, j, V, ldv, h_in, w, partial, done, rev != 0);
+  cgs_update_dots_body<T, K, true>(n, j, V, ldv, h_in, w, partial, done, rev != 0);
 }
 
 // w[r..r+3] -= sum_c V[c][r..r+3] h[c] over the j columns in ascending c: the
