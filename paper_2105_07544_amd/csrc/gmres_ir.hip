@@ -660,6 +660,32 @@ gmr_status library_stream(hipStream_t* out) {
   return GMR_OK;
 }
 
+// Makes the occupancy queries behind balanced_grid for every kernel that uses
+// it, so that none of them first happens while a cycle is being captured.
+template <class T>
+static void warm_grid_cache() {
+  const void* fns[] = {
+      reinterpret_cast<const void*>(cgs_update_dots_kernel<T, 8>),
+      reinterpret_cast<const void*>(cgs_update_dots_kernel<T, 16>),
+      reinterpret_cast<const void*>(cgs_update_dots_kernel<T, 32>),
+      reinterpret_cast<const void*>(cgs_update_dots_kernel<T, 64>),
+      reinterpret_cast<const void*>(cgs_dots4_kernel<T, 8, 1>),
+      reinterpret_cast<const void*>(cgs_dots4_kernel<T, 16, 1>),
+      reinterpret_cast<const void*>(cgs_dots4_kernel<T, 32, 1>),
+      reinterpret_cast<const void*>(cgs_dots4_kernel<T, 32, 2>),
+      reinterpret_cast<const void*>(cgs_dots4_kernel<T, 32, 4>),
+      reinterpret_cast<const void*>(cgs_dots4_kernel<T, 32, 8>),
+      reinterpret_cast<const void*>(cgs_dots4_kernel<T, 32, 16>)};
+  for (const void* f : fns) (void)resident_blocks(f);
+  if constexpr (sizeof(T) == 4) {
+    (void)resident_blocks(reinterpret_cast<const void*>(cgs_update_dots_kernel<T, 128>));
+    (void)resident_blocks(reinterpret_cast<const void*>(hb_update_dots_kernel<8>));
+    (void)resident_blocks(reinterpret_cast<const void*>(hb_update_dots_kernel<16>));
+    (void)resident_blocks(reinterpret_cast<const void*>(hb_update_dots_kernel<32>));
+    (void)resident_blocks(reinterpret_cast<const void*>(hb_update_dots_kernel<64>));
+  }
+}
+
 template <class TI, class TO>
 static gmr_status solve_impl(const SolveArgs& a) {
   const auto t_start = std::chrono::steady_clock::now();
@@ -685,6 +711,7 @@ static gmr_status solve_impl(const SolveArgs& a) {
   Ctx c{a.stream, nullptr};
   CycleGraph graph;
   graph.use = (prm.flags & GMR_FLAG_GRAPH) && prm.prof_kernel == GMR_PROF_NONE;
+  warm_grid_cache<TI>();
   if (graph.use) {
     // capture needs a stream other than the legacy default one: the solve runs
     // on the library's own stream once the caller's stream has drained
