@@ -451,3 +451,107 @@ def check_half_basis():
 
 
 ALL_CHECKS.append(check_half_basis)
+
+
+# --- O6c Leja order of the polynomial's roots -------------------------------------
+def _golden(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)))
+
+
+def check_leja_golden_order():
+    # a hand-derived ordering (tests/golden/leja_order.json) that an order by
+    # modulus, or a rule without the distance product, gets wrong
+    g = _golden("leja_order.json")
+    pts = np.array(g["points_re"]) + 1j * np.array(g["points_im"])
+    want = np.array(g["order_re"]) + 1j * np.array(g["order_im"])
+    for perm in (np.arange(6), np.arange(6)[::-1], rng(60).permutation(6)):
+        got = O.leja_order(pts[perm])
+        assert np.array_equal(got, want), (perm, got)
+
+
+def check_leja_greedy_property():
+    # brute force over the candidates at every pick: each real point and each
+    # first member of a pair maximises the product of the distances to the
+    # points already taken (the conjugate of a taken point follows it)
+    A, D = _nonsym(30, 61)
+    for d in (5, 9):
+        theta = O.poly_roots(A, d, rng(62 + d).standard_normal(30))
+        assert len(theta) == d + 1
+        assert abs(theta[0]) >= np.max(np.abs(theta)) * (1 - 1e-12)
+        i = 1 if theta[0].imag == 0 else 2
+        while i < len(theta):
+            rest = theta[i:]
+            score = [np.sum(np.log(np.abs(z - theta[:i]))) for z in rest]
+            assert score[0] >= max(score) - 1e-9 * (1 + abs(max(score))), (d, i, score)
+            if theta[i].imag != 0:
+                assert theta[i].imag > 0 and theta[i + 1] == np.conj(theta[i])
+                i += 2
+            else:
+                i += 1
+
+
+def check_leja_float32_apply_stable():
+    # the reason for the order: in float32 the roots form of a degree-40
+    # polynomial of a 2D Laplacian stays within a few float32 roundings of the
+    # float64 apply of the same roots in Leja order, while an order by
+    # decreasing modulus loses every digit (growth of the partial products)
+    A = W.laplace2d(16)
+    v = rng(63).standard_normal(A.n)
+    roots = O.poly_roots(A, 40, v)
+    y64 = O.poly_apply(A, roots, v)
+    y32 = O.poly_apply(A, roots, v, np.float32)
+    assert np.linalg.norm(y32 - y64) <= 1e-4 * np.linalg.norm(y64)
+
+
+ALL_CHECKS += [check_leja_golden_order, check_leja_greedy_property, check_leja_float32_apply_stable]
+
+
+# --- O8b block Arnoldi at a breakdown -----------------------------------------------
+def _block_exhausted_system():
+    # A = S diag(lam) S^-1 with five distinct eigenvalues, one of multiplicity 2:
+    # for a generic 4-column block the block Krylov space has dimension
+    # 4, 8, 12, 16 and then only 18, so the fourth block step finds two of
+    # its four columns dependent on the basis
+    r = rng(50)
+    lam = np.repeat([1.0, 2.0, 3.5, 5.0, 7.0], [10, 10, 10, 2, 8])
+    n = lam.size
+    S = np.eye(n) + 0.3 * r.standard_normal((n, n)) / np.sqrt(n)
+    D = S @ np.diag(lam) @ np.linalg.inv(S)
+    return dense_csr(D), D, r.standard_normal((n, 4))
+
+
+def check_block_arnoldi_breakdown():
+    A, D, Bk = _block_exhausted_system()
+    p = Bk.shape[1]
+    V0, R0, ok = O.cholqr2(Bk)
+    assert ok
+    blocks, H, k = O.block_arnoldi(A, V0, 10, np.float64)
+    assert k == 4 and H.shape == (5 * p, 4 * p), (k, H.shape)
+    Vk = np.concatenate(blocks, axis=1)
+    assert np.linalg.norm(Vk.T @ Vk - np.eye(k * p)) < 1e-12
+    top, bot = H[:k * p], H[k * p:]
+    # the rows of the last block row that belong to the dependent columns are zero
+    assert np.sum(np.linalg.norm(bot, axis=1) == 0.0) == 2
+    # A V_k = V_k H_top + W with W = Q R for an orthonormal Q: W^T W = R^T R
+    Wr = D @ Vk - Vk @ top
+    assert np.linalg.norm(Wr.T @ Wr - bot.T @ bot) <= 1e-12 * np.linalg.norm(Wr.T @ Wr)
+    # the least-squares solution of the cycle is the minimum over the block
+    # Krylov space of dimension k (explicit Krylov matrix, brute force)
+    E = np.zeros(((k + 1) * p, p))
+    E[:p] = R0
+    Y = np.linalg.lstsq(H, E, rcond=None)[0]
+    res = np.linalg.norm(Bk - D @ (Vk @ Y), axis=0)
+    K = np.concatenate([np.linalg.matrix_power(D, i) @ Bk for i in range(k)], axis=1)
+    for c in range(p):
+        z, *_ = np.linalg.lstsq(D @ K, Bk[:, c], rcond=None)
+        best = np.linalg.norm(Bk[:, c] - D @ K @ z)
+        assert np.isclose(res[c], best, rtol=1e-9), (c, res[c], best)
+    # the restarted float64 block solve, a breakdown in every cycle, reaches the dense solution
+    out = O.block_gmres_ir(A, Bk, 10, 1e-12, 40, inner=np.float64)
+    Xs = np.linalg.solve(D, Bk)
+    assert out.converged and np.allclose(out.X, Xs, rtol=0, atol=1e-9 * np.abs(Xs).max())
+
+
+ALL_CHECKS.append(check_block_arnoldi_breakdown)

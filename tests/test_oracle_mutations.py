@@ -5,11 +5,12 @@ import pytest
 import oracle
 import oracle.krylov as K
 import oracle.poly as P
+import oracle.block as O_blk
 import oracle.precond as O_pre
 import pins
 
 
-def _patch(monkeypatch, name, fn, modules=(oracle, K, P, O_pre)):
+def _patch(monkeypatch, name, fn, modules=(oracle, K, P, O_pre, O_blk)):
     for m in modules:
         if hasattr(m, name):
             monkeypatch.setattr(m, name, fn)
@@ -148,6 +149,40 @@ def half_store_identity(v, sigma):
     return np.asarray(v, dtype=np.float32)  # mistake: the basis is never rounded
 
 
+def leja_by_modulus(theta):
+    # mistake: decreasing modulus instead of the distance-product rule
+    # (pairs still adjacent, positive imaginary part first)
+    out = []
+    for t in sorted((complex(z) for z in theta if complex(z).imag >= 0), key=lambda z: -abs(z)):
+        out.append(t)
+        if t.imag != 0.0:
+            out.append(t.conjugate())
+    return np.array(out)
+
+
+def block_arnoldi_zero_r(A, V0, m, dt):
+    # mistake: at a breakdown the last block row of Hbar is left zero
+    n, p = V0.shape
+    blocks = [V0.astype(dt)]
+    H = np.zeros(((m + 1) * p, m * p))
+    k = 0
+    for j in range(m):
+        W_ = O_blk.spmm(A, blocks[j], dt)
+        Vj = np.concatenate(blocks, axis=1)
+        C1 = Vj.T @ W_
+        W_ = W_ - Vj @ C1
+        C2 = Vj.T @ W_
+        W_ = W_ - Vj @ C2
+        Q, R, ok = O_blk.cholqr2(W_)
+        H[: (j + 1) * p, j * p:(j + 1) * p] = C1 + C2
+        k = j + 1
+        if not ok:
+            break
+        H[(j + 1) * p:(j + 2) * p, j * p:(j + 1) * p] = R
+        blocks.append(Q)
+    return blocks, H[: (k + 1) * p, : k * p], k
+
+
 MUTATIONS = {
     "spmv_drop_last": ("spmv", spmv_drop_last),
     "spmv_row_index": ("spmv", spmv_row_index),
@@ -164,6 +199,8 @@ MUTATIONS = {
     "bjac_short_blocks": ("bjac_apply", bjac_short_blocks),
     "half_store_unscaled": ("half_store", half_store_unscaled),
     "half_store_identity": ("half_store", half_store_identity),
+    "leja_by_modulus": ("leja_order", leja_by_modulus),
+    "block_arnoldi_zero_r": ("block_arnoldi", block_arnoldi_zero_r),
 }
 
 FAST_CHECKS = [c for c in pins.ALL_CHECKS if c.__name__ not in
