@@ -156,6 +156,20 @@ gmr_status spmv(const gmr_csr* A, const void* x, void* y, void* stream);
 gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t ldv, void* w,
                      double* h, void* ws, size_t ws_bytes, void* stream);
 
+/* cgs2_orth without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The same kernels and the same results as
+ * cgs2_orth; its scratch (about 8.4 MB: the reduction partials and the
+ * coefficient vectors) is a static device array of the library, one copy per
+ * device, held until the process ends, so the call allocates nothing.
+ * n <= 134217728 (GMR_ERR_UNSUPPORTED beyond), other arguments and errors as
+ * cgs2_orth.  Every call on a device shares that device's array: calls that
+ * overlap on one device (two streams, two threads) race and give undefined
+ * results; calls on one stream are ordered and safe.  Nothing in the array
+ * needs to start at zero.  Asynchronous. */
+gmr_status cgs2_orth_noalloc(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t ldv, void* w,
+                             double* h, void* stream);
+
 /* Build the GMRES-polynomial preconditioner p of degree `degree` (§III-D):
  * run degree+1 Arnoldi (CGS2) steps on A from the device start vector v0
  * (n entries of A's dtype, need not be normalised) in A's precision, take the

@@ -17,7 +17,7 @@ from . import _capi
 from ._capi import GMR_F32, GMR_F64, GmresError, PROF, check
 
 __all__ = ["DeviceCSR", "Poly", "SolveResult", "workspace_bytes", "alloc_workspace", "spmv",
-           "cgs2_orth", "poly_prec_setup", "bjac_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_solve",
+           "cgs2_orth", "cgs2_orth_noalloc", "poly_prec_setup", "bjac_prec_setup", "poly_prec_apply", "gmres_solve", "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_solve",
            "fd_workspace_bytes",
            "hessenberg_eigvals", "harmonic_ritz", "leja_order", "Batch", "GmresError", "GMR_F32", "GMR_F64", "lib"]
 
@@ -129,6 +129,18 @@ def cgs2_orth(V: torch.Tensor, k: int, w: torch.Tensor, ws: Optional[torch.Tenso
     h = torch.empty(k + 1, dtype=torch.float64, device=w.device)
     check(lib().cgs2_orth(dt, n, k, _ptr(V), ld, _ptr(w), _ptr(h), _ptr(ws), ws.numel(),
                           _stream(w.device)))
+    return h
+
+
+def cgs2_orth_noalloc(V: torch.Tensor, k: int, w: torch.Tensor, h: torch.Tensor,
+                      ldv: Optional[int] = None) -> torch.Tensor:
+    """cgs2_orth with the library's static scratch array instead of a workspace:
+    the call itself allocates nothing (h, float64 with k+1 entries, is the
+    caller's).  Calls that overlap on one device race."""
+    n = w.numel()
+    ld = ldv if ldv is not None else V.shape[-1]
+    check(lib().cgs2_orth_noalloc(_dtype_code(w.dtype), n, k, _ptr(V), ld, _ptr(w), _ptr(h),
+                                  _stream(w.device)))
     return h
 
 

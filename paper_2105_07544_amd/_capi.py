@@ -22,7 +22,7 @@ PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_n
         "poly_step": 5, "residual": 6, "bjac": 7}
 
 # Every symbol include/gmres_ir.h declares.
-EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "poly_prec_setup", "poly_prec_apply",
+EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "cgs2_orth_noalloc", "poly_prec_setup", "poly_prec_apply",
             "poly_prec_destroy", "bjac_prec_bytes", "bjac_prec_setup", "prec_block_size", "poly_prec_degree", "poly_prec_roots", "poly_prec_hessenberg", "gmres_solve",
             "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_workspace_bytes", "gmres_fd_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
@@ -74,6 +74,8 @@ def load() -> C.CDLL:
     lib.spmv.restype = st
     lib.cgs2_orth.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, C.c_int64, P, P, P, C.c_size_t, P]
     lib.cgs2_orth.restype = st
+    lib.cgs2_orth_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, C.c_int64, P, P, P]
+    lib.cgs2_orth_noalloc.restype = st
     lib.poly_prec_setup.argtypes = [C.POINTER(gmr_csr), C.c_int32, P, P, C.c_size_t, C.POINTER(P), P]
     lib.poly_prec_setup.restype = st
     lib.poly_prec_apply.argtypes = [P, C.POINTER(gmr_csr), P, P, P, C.c_size_t, P]

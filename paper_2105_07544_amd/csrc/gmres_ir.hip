@@ -47,12 +47,12 @@ std::string& last_error() {
     if (s_ != GMR_OK) return s_;    \
   } while (0)
 
-static inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+static constexpr inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 static inline size_t dsize(int dtype) { return dtype == GMR_F64 ? 8 : 4; }
-static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+static constexpr inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // Grid of the SpMV-type kernels (one block per 256 rows).
-static inline int spmv_grid(int n) { return ceil_div(n, kSpmvRows); }
+static constexpr inline int spmv_grid(int n) { return ceil_div(n, kSpmvRows); }
 // Grid of the CGS dot kernels: at most kMaxRedBlocks blocks (4 per CU); each
 // writes one row of column partials.
 static inline int dots_grid(int n) { return std::max(1, std::min(ceil_div(ceil_div(n, kWave), kWavesPerBlock), kMaxRedBlocks)); }
@@ -99,8 +99,8 @@ struct Small {
   size_t partial, H, Hraw, cs, sn, g, y, h1d, h2d, h1t, h2t, inv_beta, status, end;
 };
 
-static Small small_layout(int n) {
-  Small L;
+static constexpr Small small_layout(int n) {
+  Small L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
   const size_t npart = std::max<size_t>((size_t)kMaxCols * kPartPitch, (size_t)spmv_grid(n));
@@ -1026,6 +1026,38 @@ static gmr_status fd_solve(const gmr_csr* A64, const gmr_csr* A32, const double*
 
 using namespace gmr;
 
+// ---------------------------------------------------------------------------
+// Library-owned scratch for cgs2_orth_noalloc.  Up to kNoAllocMaxN rows the
+// small workspace region (reduction partials, coefficients, status) has one
+// fixed size, which is all a standalone CGS2 step uses; every device the
+// library runs on holds one copy of the array until the process ends.  Its
+// device address comes from hipGetSymbolAddress, once per device: in host
+// code the array's name is not a device address.
+// ---------------------------------------------------------------------------
+constexpr int32_t kNoAllocMaxN = 1 << 27;  // spmv_grid(n) <= kMaxCols * kPartPitch up to here
+constexpr size_t kNoAllocScratchBytes = small_layout(1).end;
+static_assert(small_layout(kNoAllocMaxN).end == kNoAllocScratchBytes, "small region grows below kNoAllocMaxN");
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+static gmr_status noalloc_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  int dev = 0;
+  GMR_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GMR_ERR_UNSUPPORTED, "cgs2_orth_noalloc: device ordinal >= 64");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    GMR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(GMR_ERR_HIP, "cgs2_orth_noalloc: hipGetSymbolAddress returned a null address");
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return GMR_OK;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1072,6 +1104,20 @@ gmr_status cgs2_orth(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t
     scale_kernel<float><<<stream_grid(n), kBlock, 0, c.s>>>(n, (const float*)w, cs.inv_beta, (float*)w, nullptr);
   }
   return check_launch("scale_kernel");
+}
+
+gmr_status cgs2_orth_noalloc(int32_t dtype, int32_t n, int32_t k, const void* V, int64_t ldv, void* w,
+                             double* h, void* stream) {
+  if (dtype != GMR_F32 && dtype != GMR_F64) return fail(GMR_ERR_INVALID, "cgs2_orth_noalloc: unknown dtype");
+  if (n <= 0 || k < 1) return fail(GMR_ERR_INVALID, "cgs2_orth_noalloc: need n > 0 and k >= 1");
+  if (n > kNoAllocMaxN)
+    return fail(GMR_ERR_UNSUPPORTED, "cgs2_orth_noalloc: n > 134217728 exceeds the static scratch array");
+  if (k > kMaxCols) return fail(GMR_ERR_UNSUPPORTED, "cgs2_orth_noalloc: k > 512 is not supported");
+  if (ldv < n) return fail(GMR_ERR_INVALID, "cgs2_orth_noalloc: ldv < n");
+  if (!V || !w || !h) return fail(GMR_ERR_INVALID, "cgs2_orth_noalloc: null pointer");
+  void* ws = nullptr;
+  GMR_TRY(noalloc_scratch(&ws));
+  return cgs2_orth(dtype, n, k, V, ldv, w, h, ws, kNoAllocScratchBytes, stream);
 }
 
 gmr_status csr_values_to_f32(const double* in, float* out, int64_t count, void* stream) {

@@ -82,6 +82,12 @@ def test_argument_errors_before_device_work():
     assert lib.cgs2_orth(0, 10, 600, 1, 10, 1, 1, None, 0, None) == -5
     assert lib.cgs2_orth(0, 10, 3, 1, 5, 1, 1, None, 0, None) == -1
     assert lib.cgs2_orth(0, 10, 3, 1, 10, 1, 1, None, 0, None) == -3
+    # the no-allocation variant: its size limit and argument checks come before any HIP call
+    assert lib.cgs2_orth_noalloc(2, 10, 3, 1, 10, 1, 1, None) == -1
+    assert lib.cgs2_orth_noalloc(0, (1 << 27) + 1, 3, 1, (1 << 27) + 1, 1, 1, None) == -5
+    assert lib.cgs2_orth_noalloc(0, 10, 513, 1, 10, 1, 1, None) == -5
+    assert lib.cgs2_orth_noalloc(0, 10, 3, 1, 9, 1, 1, None) == -1
+    assert lib.cgs2_orth_noalloc(0, 10, 3, None, 10, 1, 1, None) == -1
     assert lib.poly_prec_setup(C.byref(A), 129, 1, None, 0, C.byref(C.c_void_p()), None) == -5
     assert lib.spmv(C.byref(A), 5, 5, None) == -1
 
