@@ -33,16 +33,19 @@ __global__ __launch_bounds__(kBlock) void spmv_hb_kernel(int n, const int* __res
                                                          const double* __restrict__ scale, float sigma,
                                                          half_t* __restrict__ vout, float* __restrict__ y,
                                                          const int* __restrict__ done) {
-  __shared__ float s_prod[kSpmvChunk];
-  __shared__ int s_rp[kSpmvRows + 1];
+  __shared__ __align__(16) float s_prod[SpmvCfg<float>::kChunk];
   if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
-  const int r = r0 + threadIdx.x;
   const float s = float(*scale);
-  const float acc = spmv_row<float, true>(n, r0, rp, ci, val, x, s, s_prod, s_rp);
-  if (r < n) {
-    vout[r] = half_t((x[r] * s) * sigma);
-    y[r] = acc;
+  float acc[kSpmvRpt];
+  spmv_rows<float, true>(n, r0, rp, ci, val, x, s, s_prod, acc);
+#pragma unroll
+  for (int i = 0; i < kSpmvRpt; ++i) {
+    const int r = r0 + threadIdx.x + i * kBlock;
+    if (r < n) {
+      vout[r] = half_t((x[r] * s) * sigma);
+      y[r] = acc[i];
+    }
   }
 }
 

@@ -21,9 +21,27 @@
 
 namespace gmr {
 
-// Rows handled by one SpMV block and nonzeros staged in LDS per pass.
-constexpr int kSpmvRows = 256;
-constexpr int kSpmvChunk = 2048;
+// Rows of an SpMV-type kernel per thread and per block of kBlock threads:
+// thread t owns rows r0 + t + i * kBlock, i < kSpmvRpt.  Two rows per thread
+// halve the blocks (and the row-pointer / barrier overhead per row) and keep
+// twice the (index, value) loads of a thread in flight.
+#ifndef GMR_SPMV_RPT
+#define GMR_SPMV_RPT 2
+#endif
+constexpr int kSpmvRpt = GMR_SPMV_RPT;
+constexpr int kSpmvRows = kBlock * kSpmvRpt;
+// Nonzeros staged in LDS per pass (16 KB of float32 or 32 KB of float64
+// products): a block of 512 rows with up to 8 nonzeros per row takes one pass.
+// Measured on the 3D Laplacian 150^3 and the 2500^2 five-point matrix against
+// one row per thread and against 8 or 16 KB passes, this is the fastest form
+// in float32 (46.8 / 61.2 us) and in float64 (71.8 / 94.9 us).
+#ifndef GMR_SPMV_CHUNK
+#define GMR_SPMV_CHUNK 4096
+#endif
+template <class T>
+struct SpmvCfg {
+  static constexpr int kChunk = GMR_SPMV_CHUNK;
+};
 // Upper bound on the number of blocks of a reduction kernel (partials per column).
 constexpr int kMaxRedBlocks = 1024;
 // Basis columns (j) supported by the kernels; H has restart+1 rows.
@@ -97,31 +115,53 @@ __device__ __forceinline__ void load_quad(const int* __restrict__ ci, const T* _
   }
 }
 
-// Computes, for thread t of the block, the dot product of row (r0 + t) with x
-// (x scaled by `s` when SCALED).  Returns 0 for threads past the last row.
-// The block's nonzeros are processed in passes of kSpmvChunk entries that
-// start on a multiple of 4: each thread loads up to two quads of (col, val)
-// with vector loads (none past the block's last nonzero), gathers x for the
-// entries that belong to the block, stores the rounded products in LDS, and
-// then adds up its own row in ascending k.
-template <class T, bool SCALED>
-__device__ __forceinline__ T spmv_row(int n, int r0, const int* __restrict__ rp,
-                                      const int* __restrict__ ci, const T* __restrict__ val,
-                                      const T* __restrict__ x, T s, T* s_prod, int* s_rp) {
-  __shared__ int s_nnz;
+// Four consecutive products into LDS at a 4-aligned slot (16-byte aligned
+// for float, two 16-byte stores for double).
+template <class T>
+__device__ __forceinline__ void store_quad(T* dst, const T (&p)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<fvec4_t*>(dst) = fvec4_t{p[0], p[1], p[2], p[3]};
+  } else {
+    reinterpret_cast<dvec2_t*>(dst)[0] = dvec2_t{p[0], p[1]};
+    reinterpret_cast<dvec2_t*>(dst)[1] = dvec2_t{p[2], p[3]};
+  }
+}
+
+// Computes, for thread t of the block, the dot products of rows
+// r0 + t + i * kBlock (i < kSpmvRpt) with x (x scaled by `s` when SCALED) into
+// acc[i]; 0 for rows past the last one.  The block's nonzeros are processed in
+// passes of SpmvCfg<T>::kChunk entries that start on a multiple of 4.  In a
+// pass each thread takes up to Q quads of (col, val) with vector loads (none
+// past the block's last nonzero), gathers x for them, and stores the four
+// rounded products into LDS with one vector store; after a barrier every
+// thread adds up its own rows in ascending k (so the pass length CH does not
+// change the result).  Entries of a quad that belong to a neighbouring block
+// (before k0 or from k1 on) produce products in LDS slots no row of this
+// block reads, so no per-entry masking is needed.  The
+// row bounds come straight from global memory: the block's first and last
+// (uniform, scalar loads) and each thread's own, with no LDS staging and no
+// barrier before the nonzero loads are issued.
+template <class T, bool SCALED, int CH = SpmvCfg<T>::kChunk>
+__device__ __forceinline__ void spmv_rows(int n, int r0, const int* __restrict__ rp,
+                                          const int* __restrict__ ci, const T* __restrict__ val,
+                                          const T* __restrict__ x, T s, T* s_prod, T (&acc)[kSpmvRpt]) {
+  constexpr int Q = CH / (4 * kBlock);  // quads per thread per pass
   const int t = threadIdx.x;
   const int nr = min(kSpmvRows, n - r0);
-  for (int i = t; i <= nr; i += kBlock) s_rp[i] = rp[r0 + i];
-  if (t == 0) s_nnz = rp[n];
-  __syncthreads();
-  const int k0 = s_rp[0];
-  const int k1 = s_rp[nr];
-  const int nnz = s_nnz;
-  const int rs = (t < nr) ? s_rp[t] : 0;
-  const int re = (t < nr) ? s_rp[t + 1] : 0;
-  T acc = T(0);
-  constexpr int Q = kSpmvChunk / (4 * kBlock);  // quads per thread per pass
-  for (int base = k0 & ~3; base < k1; base += kSpmvChunk) {
+  const int k0 = rp[r0];
+  const int k1 = rp[r0 + nr];
+  const int nnz = rp[n];
+  int rs[kSpmvRpt], re[kSpmvRpt];
+#pragma unroll
+  for (int i = 0; i < kSpmvRpt; ++i) {
+    const int rl = t + i * kBlock;
+    rs[i] = (rl < nr) ? rp[r0 + rl] : 0;
+    re[i] = (rl < nr) ? rp[r0 + rl + 1] : 0;
+    acc[i] = T(0);
+  }
+  for (int base = k0 & ~3; base < k1; base += CH) {
+    // all loads of the pass are issued before the first one is waited for:
+    // the quads, then the gathers (a quad past k1 gathers x[0], in bounds)
     int col[Q][4];
     T a[Q][4];
 #pragma unroll
@@ -129,7 +169,7 @@ __device__ __forceinline__ T spmv_row(int n, int r0, const int* __restrict__ rp,
       const int kk = base + 4 * (t + q * kBlock);
       if (kk < k1) {
         load_quad<T>(ci, val, kk, nnz, col[q], a[q]);
-      } else {  // the quad lies past the block's last row: nothing to load
+      } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           col[q][i] = 0;
@@ -137,30 +177,32 @@ __device__ __forceinline__ T spmv_row(int n, int r0, const int* __restrict__ rp,
         }
       }
     }
-    T xv[Q][4];
+    T v[Q][4];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = base + 4 * (t + q * kBlock) + i;
-        xv[q][i] = (k >= k0 && k < k1) ? x[col[q][i]] : T(0);
-      }
+      for (int i = 0; i < 4; ++i) v[q][i] = x[col[q][i]];
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+    for (int q = 0; q < Q; ++q) {
+      const int kk = base + 4 * (t + q * kBlock);
+      T p[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int k = base + 4 * (t + q * kBlock) + i;
-        T v = xv[q][i];
-        if constexpr (SCALED) v = v * s;
-        if (k >= k0 && k < k1) s_prod[k - base] = a[q][i] * v;
+        T xv = v[q][i];
+        if constexpr (SCALED) xv = xv * s;
+        p[i] = a[q][i] * xv;
       }
+      if (kk < k1) store_quad<T>(s_prod + (kk - base), p);
+    }
     __syncthreads();
-    const int lo = max(rs, base);
-    const int hi = min(re, base + kSpmvChunk);
-    for (int k = lo; k < hi; ++k) acc += s_prod[k - base];
+#pragma unroll
+    for (int i = 0; i < kSpmvRpt; ++i) {
+      const int lo = max(rs[i], base);
+      const int hi = min(re[i], base + CH);
+      for (int k = lo; k < hi; ++k) acc[i] += s_prod[k - base];
+    }
     __syncthreads();
   }
-  return acc;
 }
 
 // y = A x.  When `scale` is non-null the input is x * (*scale) and, when `vout`
@@ -174,20 +216,28 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n, const int* __restri
                                                       const double* __restrict__ scale,
                                                       T* __restrict__ vout, T* __restrict__ y,
                                                       const int* __restrict__ done) {
-  __shared__ T s_prod[kSpmvChunk];
-  __shared__ int s_rp[kSpmvRows + 1];
+  __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
   if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
-  const int r = r0 + threadIdx.x;
-  T acc;
+  T acc[kSpmvRpt];
   if (scale) {
     const T s = T(*scale);
-    acc = spmv_row<T, true>(n, r0, rp, ci, val, x, s, s_prod, s_rp);
-    if (r < n && vout) vout[r] = x[r] * s;
+    spmv_rows<T, true>(n, r0, rp, ci, val, x, s, s_prod, acc);
+    if (vout) {
+#pragma unroll
+      for (int i = 0; i < kSpmvRpt; ++i) {
+        const int r = r0 + threadIdx.x + i * kBlock;
+        if (r < n) vout[r] = x[r] * s;
+      }
+    }
   } else {
-    acc = spmv_row<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, s_rp);
+    spmv_rows<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, acc);
   }
-  if (r < n) y[r] = acc;
+#pragma unroll
+  for (int i = 0; i < kSpmvRpt; ++i) {
+    const int r = r0 + threadIdx.x + i * kBlock;
+    if (r < n) y[r] = acc[i];
+  }
 }
 
 // r = b - A x with the block's partial ||r||^2 (float64) in partial[blockIdx.x];
@@ -199,16 +249,19 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(int n, const int* __re
                                                           const T* __restrict__ x,
                                                           const T* __restrict__ b,
                                                           T* __restrict__ r, double* partial) {
-  __shared__ T s_prod[kSpmvChunk];
-  __shared__ int s_rp[kSpmvRows + 1];
+  __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
-  const int row = r0 + threadIdx.x;
-  T acc = spmv_row<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, s_rp);
+  T acc[kSpmvRpt];
+  spmv_rows<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, acc);
   double sq = 0.0;
-  if (row < n) {
-    T rv = b[row] - acc;
-    r[row] = rv;
-    sq = double(rv) * double(rv);
+#pragma unroll
+  for (int i = 0; i < kSpmvRpt; ++i) {
+    const int row = r0 + threadIdx.x + i * kBlock;
+    if (row < n) {
+      T rv = b[row] - acc[i];
+      r[row] = rv;
+      sq += double(rv) * double(rv);
+    }
   }
   sq = block_sum(sq);
   if (threadIdx.x == 0) partial[blockIdx.x] = sq;
@@ -858,16 +911,19 @@ __global__ __launch_bounds__(kBlock) void poly_real_kernel(int n, const int* __r
                                                            const T* __restrict__ P, T c,
                                                            T* __restrict__ Y, T* __restrict__ Pn,
                                                            const int* __restrict__ done) {
-  __shared__ T s_prod[kSpmvChunk];
-  __shared__ int s_rp[kSpmvRows + 1];
+  __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
   if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
-  const int r = r0 + threadIdx.x;
-  const T ap = spmv_row<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, s_rp);
-  if (r < n) {
-    const T p = P[r];
-    Y[r] = FIRST ? c * p : Y[r] + c * p;
-    Pn[r] = p - c * ap;
+  T ap[kSpmvRpt];
+  spmv_rows<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, ap);
+#pragma unroll
+  for (int i = 0; i < kSpmvRpt; ++i) {
+    const int r = r0 + threadIdx.x + i * kBlock;
+    if (r < n) {
+      const T p = P[r];
+      Y[r] = FIRST ? c * p : Y[r] + c * p;
+      Pn[r] = p - c * ap[i];
+    }
   }
 }
 
@@ -889,17 +945,20 @@ __global__ __launch_bounds__(kBlock) void poly_pair1_kernel(int n, const int* __
                                                             const T* __restrict__ P, T c1, T c2,
                                                             T* __restrict__ Y, T* __restrict__ Tt,
                                                             const int* __restrict__ done) {
-  __shared__ T s_prod[kSpmvChunk];
-  __shared__ int s_rp[kSpmvRows + 1];
+  __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
   if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
-  const int r = r0 + threadIdx.x;
-  const T t = spmv_row<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, s_rp);
-  if (r < n) {
-    const T p = P[r];
-    Tt[r] = t;
-    const T inc = c1 * p - c2 * t;
-    Y[r] = FIRST ? inc : Y[r] + inc;
+  T t[kSpmvRpt];
+  spmv_rows<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, t);
+#pragma unroll
+  for (int i = 0; i < kSpmvRpt; ++i) {
+    const int r = r0 + threadIdx.x + i * kBlock;
+    if (r < n) {
+      const T p = P[r];
+      Tt[r] = t[i];
+      const T inc = c1 * p - c2 * t[i];
+      Y[r] = FIRST ? inc : Y[r] + inc;
+    }
   }
 }
 
@@ -912,13 +971,16 @@ __global__ __launch_bounds__(kBlock) void poly_pair2_kernel(int n, const int* __
                                                             const T* __restrict__ Tt, T c1, T c2,
                                                             T* __restrict__ Pn,
                                                             const int* __restrict__ done) {
-  __shared__ T s_prod[kSpmvChunk];
-  __shared__ int s_rp[kSpmvRows + 1];
+  __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
   if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
-  const int r = r0 + threadIdx.x;
-  const T at = spmv_row<T, false>(n, r0, rp, ci, val, Tt, T(1), s_prod, s_rp);
-  if (r < n) Pn[r] = P[r] - (c1 * Tt[r] - c2 * at);
+  T at[kSpmvRpt];
+  spmv_rows<T, false>(n, r0, rp, ci, val, Tt, T(1), s_prod, at);
+#pragma unroll
+  for (int i = 0; i < kSpmvRpt; ++i) {
+    const int r = r0 + threadIdx.x + i * kBlock;
+    if (r < n) Pn[r] = P[r] - (c1 * Tt[r] - c2 * at[i]);
+  }
 }
 
 // ===========================================================================
@@ -987,9 +1049,10 @@ __global__ __launch_bounds__(kBlock) void small_cycle_kernel(
     const TO* __restrict__ b, TO* __restrict__ x, TO* __restrict__ r, TI* V,
     int64_t ldv, TI* w0, TI* w1, CycleState cs, double* partial, TI* h1t, TI* h2t, int mc, double stop_rel,
     double thresh) {
-  __shared__ TI s_pi[kSpmvChunk];
-  __shared__ TO s_po[kSpmvChunk];
-  __shared__ int s_rp[kSpmvRows + 1];
+  // passes of 2048 entries keep the single block's LDS within 160 KB
+  constexpr int kSmallChunk = 2048;
+  __shared__ __align__(16) TI s_pi[kSmallChunk];
+  __shared__ __align__(16) TO s_po[kSmallChunk];
   Status* st = cs.st;
   start_cycle_body<TO, TI>(n, r, w0, partial, st);
   __syncthreads();
@@ -1007,14 +1070,18 @@ __global__ __launch_bounds__(kBlock) void small_cycle_kernel(
     TI* vj = V + (size_t)j * ldv;
     const TI s = TI(*cs.inv_beta);
     for (int r0 = 0; r0 < n; r0 += kSpmvRows) {
-      const TI acc = spmv_row<TI, true>(n, r0, rp, ci, vin, wc, s, s_pi, s_rp);
-      const int row = r0 + threadIdx.x;
-      if (row < n) {
-        vj[row] = wc[row] * s;
-        wn[row] = acc;
+      TI acc[kSpmvRpt];
+      spmv_rows<TI, true, kSmallChunk>(n, r0, rp, ci, vin, wc, s, s_pi, acc);
+#pragma unroll
+      for (int i = 0; i < kSpmvRpt; ++i) {
+        const int row = r0 + threadIdx.x + i * kBlock;
+        if (row < n) {
+          vj[row] = wc[row] * s;
+          wn[row] = acc[i];
+        }
       }
-      __syncthreads();  // s_rp is reloaded by the next chunk
     }
+    __syncthreads();  // wn and vj complete before the CGS2 passes read them
     small_cgs2<TI>(n, j + 1, V, ldv, wn, partial, cs, h1t, h2t, mc - 1, thresh);
     TI* t = wc;
     wc = wn;
@@ -1024,14 +1091,17 @@ __global__ __launch_bounds__(kBlock) void small_cycle_kernel(
   __syncthreads();
   double sq = 0.0;
   for (int r0 = 0; r0 < n; r0 += kSpmvRows) {
-    const TO acc = spmv_row<TO, false>(n, r0, rpo, cio, vout, x, TO(1), s_po, s_rp);
-    const int row = r0 + threadIdx.x;
-    if (row < n) {
-      const TO rv = b[row] - acc;
-      r[row] = rv;
-      sq += double(rv) * double(rv);
+    TO acc[kSpmvRpt];
+    spmv_rows<TO, false, kSmallChunk>(n, r0, rpo, cio, vout, x, TO(1), s_po, acc);
+#pragma unroll
+    for (int i = 0; i < kSpmvRpt; ++i) {
+      const int row = r0 + threadIdx.x + i * kBlock;
+      if (row < n) {
+        const TO rv = b[row] - acc[i];
+        r[row] = rv;
+        sq += double(rv) * double(rv);
+      }
     }
-    __syncthreads();
   }
   sq = block_sum(sq);
   if (threadIdx.x == 0) {
