@@ -24,9 +24,15 @@ Other workloads (each prints its own line; the default line is the one above):
              matrix: GMRES-IR with float32 blocks vs float64 GMRES
   restart    restart lengths 25..400 on the 3D Laplacian 150^3 (b = ones)
 
-Extra fields: the float64 GMRES time on the same GPU and the ratio,
+Extra fields of the default line: the float64 GMRES time on the same GPU and
+the ratio, the per-restart residual table (GMRES-IR's explicit residual beside
+float64 GMRES's at the same restart), the float32-only GMRES residual,
 per-kernel-family time and GB/s (the analogue of the paper's Table I), the
-roofline of the dominant kernel, and the oracle's time on the host CPU.
+roofline of the dominant kernel from separately bracketed solves, the oracle's
+time on one host core (extrapolated, with a check of the fit), and `configs`:
+the same IR-vs-float64 record for the 2D Laplacian 64^2, the 2500^2
+convection-diffusion problem with the degree-25 polynomials, and the batch of
+256 systems x 16 right-hand sides (--no-configs leaves them out).
 """
 from __future__ import annotations
 
@@ -145,53 +151,83 @@ def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, kernel: str, pa
         print(f"\nread ratio float64 / float32: {reads['spmv_kernel<double'] / reads['spmv_kernel<float']:.3f}")
 
 
-def cpu_threads():
-    try:
-        from threadpoolctl import threadpool_info
-        info = threadpool_info()
-        return max(d.get("num_threads", 1) for d in info) if info else 1
-    except Exception:
-        return os.cpu_count() or 1
-
-
 def cpu_baseline(problem, cycles_full: int, m: int, prec32=None, ks=(1, 4, 10)):
-    """The oracle on the host: prefix runs of a few inner iterations of the
-    same solve fix a per-iteration cost a + b*j (j = basis size) and the
-    per-run overhead; the full solve is extrapolated to the GPU's cycle count."""
+    """The oracle on one host core (BLAS held to one thread; the oracle's SpMV
+    is a single-threaded numpy loop): prefix runs of a few inner iterations of
+    the same solve fix a per-iteration cost a + b*j (j = basis size) and the
+    per-run overhead, and the full solve is extrapolated to the GPU's cycle
+    count.  The same fit is then checked once against a complete oracle solve
+    of the 3D Laplacian at N = 60 (fit from prefixes, measured to 1e-10)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import oracle as O
-    A, b = problem.A, problem.b
-    t0 = time.perf_counter()
-    O.spmv(A, b, np.float64)
-    t_res = time.perf_counter() - t0
-    ts = []
-    for k in ks:
+    import workloads as W
+
+    def fit(prob, cycles, mm, pre, kk):
+        A, b = prob.A, prob.b
         t0 = time.perf_counter()
-        O.gmres_ir(A, b, np.zeros(A.n), m, 1e-10, k, prec32=prec32)
-        ts.append(time.perf_counter() - t0)
-        log(f"cpu_baseline: oracle GMRES-IR prefix of {k} iterations: {ts[-1]:.2f} s")
-    # T(k) = c0 + a k + b k(k+1)/2
-    M = np.array([[1.0, k, k * (k + 1) / 2.0] for k in ks])
-    c0, a, bb = np.linalg.solve(M, np.array(ts))
-    t_cycle = (c0 + a * m + bb * m * (m + 1) / 2.0) - t_res
-    est = t_res + cycles_full * t_cycle
-    return {"value": float(est), "unit": "s", "cores": int(cpu_threads()), "kind": "oracle",
-            "sample": (f"oracle GMRES-IR on the same workload, prefixes of {list(ks)} inner iterations "
-                       f"({sum(ts):.1f} s of CPU work); cost a+b*j per iteration and the "
+        O.spmv(A, b, np.float64)
+        t_res = time.perf_counter() - t0
+        ts = []
+        for k in kk:
+            t0 = time.perf_counter()
+            O.gmres_ir(A, b, np.zeros(A.n), mm, 1e-10, k, prec32=pre)
+            ts.append(time.perf_counter() - t0)
+            log(f"cpu_baseline: oracle GMRES-IR (n={A.n}) prefix of {k} iterations: {ts[-1]:.2f} s")
+        # T(k) = c0 + a k + b k(k+1)/2
+        M = np.array([[1.0, k, k * (k + 1) / 2.0] for k in kk])
+        c0, a, bb = np.linalg.solve(M, np.array(ts))
+        t_cycle = (c0 + a * mm + bb * mm * (mm + 1) / 2.0) - t_res
+        return t_res + cycles * t_cycle, sum(ts)
+
+    with threadpool_limits(limits=1):
+        est, spent = fit(problem, cycles_full, m, prec32, ks)
+        small = W.config2_laplace3d(N=60, restart=50)
+        t0 = time.perf_counter()
+        ref = O.gmres_ir(small.A, small.b, np.zeros(small.A.n), 50, 1e-10, 100000)
+        t_full = time.perf_counter() - t0
+        pred, spent_small = fit(small, ref.cycles, 50, None, (3, 10, 24))
+    log(f"cpu_baseline: fit check at N=60: predicted {pred:.2f} s, measured {t_full:.2f} s")
+    return {"value": float(est), "unit": "s", "cores": 1, "kind": "oracle", "extrapolated": True,
+            "sample": (f"oracle GMRES-IR on the same workload on one core, prefixes of {list(ks)} inner "
+                       f"iterations ({spent:.1f} s of CPU work); cost a+b*j per iteration and the "
                        f"per-run overhead fitted, extrapolated to {cycles_full} cycles of m={m}"),
-            "sample_seconds": float(sum(ts))}
+            "sample_seconds": float(spent),
+            "host_cores": os.cpu_count(),
+            "fit_check": {"workload": "3D Laplacian 60^3, GMRES(50)-IR to 1e-10, oracle on one core",
+                          "cycles": int(ref.cycles), "predicted_s": round(pred, 3),
+                          "measured_s": round(t_full, 3), "rel_error": round(pred / t_full - 1.0, 4),
+                          "sample_seconds": round(spent_small + t_full, 2)}}
 
 
-def single_system(args, kind):
+def residual_table(ir, f64, m: int):
+    """Per restart k: GMRES-IR's explicit ||b - A x_k|| / ||b|| beside float64
+    GMRES(m)'s explicit residual at the end of its k-th cycle (iteration k*m,
+    or its mid-cycle stop in the last cycle); both histories start at x0."""
+    rows = []
+    for k in range(max(len(ir.history), len(f64.history))):
+        rows.append({"k": k, "iter": min(k * m, ir.iters) if k < len(ir.history) else None,
+                     "ir": ir.history[k] if k < len(ir.history) else None,
+                     "fp64": f64.history[k] if k < len(f64.history) else None})
+    return rows
+
+
+def single_system(args, kind, steps=None, warmup=None, breakdown=True, extras=True, cpu=True):
+    """One single-system config: GMRES-IR (float32 inner) against float64
+    GMRES on the same GPU.  `value` is the mean of `steps` unprofiled IR solves;
+    the roofline comes from separate solves whose dominant-kernel launches are
+    bracketed by HIP events on the solver's stream."""
     import numpy as np
     import torch
 
     import paper_2105_07544_amd as G
     import workloads as W
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     dev = "cuda:0"
-    log("bench: building the workload")
+    log(f"bench: building the workload ({kind})")
     if kind == "laplace3d":
         N = args.grid or 150
         prob = W.config2_laplace3d(N=N, restart=args.restart or 50)
@@ -226,6 +262,14 @@ def single_system(args, kind):
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
     graph = bool(args.graph)
+    Ah = host_csr(prob.A)
+
+    def host_err():
+        xh = x.cpu().numpy()
+        rel = float(np.linalg.norm(prob.b - Ah @ xh) / np.linalg.norm(prob.b))
+        fwd = (float(np.linalg.norm(xh - prob.x_true) / np.linalg.norm(prob.x_true))
+               if prob.x_true is not None else None)
+        return rel, fwd
 
     # small systems run each restart cycle as one single-block kernel
     pers = (args.persistent == 1) or (args.persistent < 0 and prob.A.n <= 1024)
@@ -241,73 +285,75 @@ def single_system(args, kind):
                              prof=prof, graph=graph if g is None else g, persistent=pers)[1]
 
     log("bench: warmup")
-    unprof = [ir().seconds for _ in range(args.warmup)]
-    # timed region: K complete GMRES-IR solves; every launch of the dominant
-    # kernel is bracketed by HIP events on the solver's stream (graph replay and
-    # the single-block cycle have no per-kernel events: then K more multi-kernel
-    # solves give them)
-    log(f"bench: timing {args.steps} GMRES-IR solves")
+    for _ in range(warmup):
+        ir()
+    # timed region: `steps` complete GMRES-IR solves, nothing bracketed
+    log(f"bench: timing {steps} GMRES-IR solves")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    eager_events = not (graph or pers)  # graph replay and the single-block cycle have no per-kernel events
-    res = [ir(prof=dominant if eager_events else "none") for _ in range(args.steps)]
+    res = [ir() for _ in range(steps)]
     torch.cuda.synchronize()
-    t_ir = (time.perf_counter() - t0) / args.steps
-    pres = res if eager_events else [ir(prof=dominant, g=False) for _ in range(args.steps)]
+    t_ir = (time.perf_counter() - t0) / steps
     last = res[-1]
     assert all(r.converged for r in res), [r.status_name for r in res]
-    xh = x.cpu().numpy()
-    rel = float(np.linalg.norm(prob.b - host_csr(prob.A) @ xh) / np.linalg.norm(prob.b))
-    fwd = float(np.linalg.norm(xh - prob.x_true) / np.linalg.norm(prob.x_true))
+    rel, fwd = host_err()
+    log(f"bench: IR {t_ir:.4f} s/solve, {last.iters} iters, {last.cycles} cycles")
+
+    log("bench: float64 GMRES")
+    f64()
+    nf = max(1, min(steps, 3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r64 = [f64() for _ in range(nf)]
+    torch.cuda.synchronize()
+    t_64 = (time.perf_counter() - t0) / nf
+    assert all(r.converged for r in r64), [r.status_name for r in r64]
+    rel64, fwd64 = host_err()
+
+    # the roofline of the dominant kernel: separate solves, every launch of it
+    # bracketed by events (graph replay and the single-block cycle have none)
+    npro = max(1, min(steps, 5))
+    pres = [ir(prof=dominant, g=False) for _ in range(npro)]
     prof_ms = sum(r.prof_ms for r in pres)
     prof_bytes = sum(r.prof_bytes for r in pres)
     prof_launches = sum(r.prof_launches for r in pres)
     achieved = prof_bytes / (prof_ms * 1e-3) / 1e9 if prof_ms > 0 else 0.0
-    log(f"bench: IR {t_ir:.3f} s/solve, {last.iters} iters, {last.cycles} cycles")
-
-    log("bench: float64 GMRES")
-    f64()
-    t0 = time.perf_counter()
-    r64 = [f64() for _ in range(max(1, min(args.steps, 3)))]
-    t_64 = (time.perf_counter() - t0) / len(r64)
-    assert all(r.converged for r in r64), [r.status_name for r in r64]
 
     half = None
-    if not degree and prob.A.n > 1024:
+    if extras and not degree and prob.A.n > 1024:
         # the third precision (float16 basis), reported beside the paper's method
         log("bench: GMRES-IR with the float16 basis")
         x.zero_()
         G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir, half_basis=True)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         rh = [G.gmres_ir_solve(A64, A32, b, x.zero_(), restart=m, tol=1e-10, max_iters=200000, ws=ws_ir,
-                               half_basis=True)[1] for _ in range(max(1, min(args.steps, 3)))]
-        t_h = (time.perf_counter() - t0) / len(rh)
-        xh16 = x.cpu().numpy()
-        rel16 = float(np.linalg.norm(prob.b - host_csr(prob.A) @ xh16) / np.linalg.norm(prob.b))
+                               half_basis=True)[1] for _ in range(nf)]
+        t_h = (time.perf_counter() - t0) / nf
+        rel16, _ = host_err()
         half = {"seconds": round(t_h, 5), "iters": rh[-1].iters, "cycles": rh[-1].cycles, "rel_res": rel16,
                 "speedup_vs_fp64": round(t_64 / t_h, 3), "speedup_vs_f32_basis": round(t_ir / t_h, 3)}
         assert all(r.converged for r in rh) and rel16 <= 1e-10, half
-        if not args.no_breakdown:
+        if breakdown and not args.no_breakdown:
             for fam in ("spmv", "cgs_dots", "cgs_update_dots", "cgs_update_norm"):
                 x.zero_()
                 rp = G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir,
                                       half_basis=True, prof=fam)[1]
                 half[fam + "_gbs"] = round(rp.prof_bytes / (rp.prof_ms * 1e-3) / 1e9, 1) if rp.prof_ms else None
                 half[fam + "_ms"] = round(rp.prof_ms, 3)
-    if degree and prob.A.n > 1024:
+    if extras and degree and prob.A.n > 1024:
         log("bench: GMRES-IR + float32 polynomial with the float16 basis")
         x.zero_()
         t0 = time.perf_counter()
         _, rh = G.gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_ir, P=P32,
                                  half_basis=True)
         t_h = time.perf_counter() - t0
-        xh16 = x.cpu().numpy()
-        rel16 = float(np.linalg.norm(prob.b - host_csr(prob.A) @ xh16) / np.linalg.norm(prob.b))
+        rel16, _ = host_err()
         half = {"seconds": round(t_h, 5), "iters": rh.iters, "cycles": rh.cycles, "rel_res": rel16,
                 "speedup_vs_fp64": round(t_64 / t_h, 3), "speedup_vs_f32_basis": round(t_ir / t_h, 3)}
         assert rh.converged and rel16 <= 1e-10, half
     mixed = None
-    if degree:
+    if extras and degree:
         # the middle option of §V-C: float64 GMRES with the float32 polynomial
         log("bench: float64 GMRES with the float32 polynomial")
         x.zero_()
@@ -315,30 +361,41 @@ def single_system(args, kind):
         _, rmx = G.gmres_f32prec_solve(A64, A32, P32, b, x, restart=m, tol=1e-10, max_iters=200000, ws=ws_64)
         mixed = {"seconds": round(time.perf_counter() - t0, 5), "status": rmx.status_name, "iters": rmx.iters,
                  "loss_of_accuracy": rmx.loss_of_accuracy}
-    breakdown = {}
-    if not args.no_breakdown:
+    # float32-only GMRES(m) on the same system: where float32 arithmetic alone
+    # stalls (§V-B), which is what the float64 outer loop of IR removes
+    f32only = None
+    if not degree:
+        b32 = b.float()
+        x32 = torch.zeros_like(b32)
+        _, r32 = G.gmres_solve(A32, b32, x32, restart=m, tol=1e-10, max_iters=40 * m, ws=ws_ir)
+        xh = x32.double().cpu().numpy()
+        f32only = {"status": r32.status_name, "iters": r32.iters,
+                   "rel_res": float(np.linalg.norm(prob.b - Ah @ xh) / np.linalg.norm(prob.b))}
+    breakdown_d = {}
+    if breakdown and not args.no_breakdown:
         log("bench: per-kernel breakdown")
         for fam in FAMILIES:
             if fam == "poly_step" and not degree:
                 continue
             ri, rd = ir(prof=fam, g=False), f64(prof=fam, g=False)
-            breakdown[fam] = {
+            breakdown_d[fam] = {
                 "ir_ms": round(ri.prof_ms, 3), "ir_launches": ri.prof_launches,
                 "ir_gbs": round(ri.prof_bytes / (ri.prof_ms * 1e-3) / 1e9, 1) if ri.prof_ms > 0 else None,
                 "f64_ms": round(rd.prof_ms, 3), "f64_launches": rd.prof_launches,
                 "f64_gbs": round(rd.prof_bytes / (rd.prof_ms * 1e-3) / 1e9, 1) if rd.prof_ms > 0 else None,
             }
     out = {
-        "metric": METRIC, "value": round(t_ir, 5), "unit": "s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(t_ir * 1e3, 3), "higher_is_better": False,
+        "metric": METRIC, "value": round(t_ir, 5), "unit": "s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(t_ir * 1e3, 3), "higher_is_better": False,
         "scaling": "strong", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": desc, "n": prob.A.n, "nnz": prob.A.nnz, "restart": m, "tol": 1e-10,
                    "poly_degree": degree, "inner": "f32", "outer": "f64"},
         "fp64_gmres_s": round(t_64, 5), "ir_speedup_vs_fp64": round(t_64 / t_ir, 3),
         "ir_iters": last.iters, "ir_cycles": last.cycles,
         "fp64_iters": r64[-1].iters, "fp64_cycles": r64[-1].cycles,
-        "rel_res": rel, "forward_error": fwd,
-        "ms_per_step_unprofiled": round(1e3 * float(np.median(unprof)), 3) if unprof else None,
+        "rel_res": rel, "forward_error": fwd, "fp64_rel_res": rel64, "fp64_forward_error": fwd64,
+        "residual_table": residual_table(last, r64[-1], m),
+        **({"fp32_only_gmres": f32only} if f32only else {}),
         "graph": graph, "persistent_cycle": pers,
         **({"fp64_gmres_f32poly": mixed} if mixed else {}),
         **({"ir_half_basis": half} if half else {}),
@@ -346,10 +403,11 @@ def single_system(args, kind):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": stored_traffic(dominant, kind), "launches": prof_launches,
                      "avg_launch_us": round(1e3 * prof_ms / max(1, prof_launches), 2),
-                     "bytes_per_launch": round(prof_bytes / max(1, prof_launches))},
-        "kernel_breakdown": breakdown,
+                     "bytes_per_launch": round(prof_bytes / max(1, prof_launches)),
+                     "solves": npro},
+        **({"kernel_breakdown": breakdown_d} if breakdown_d else {}),
     }
-    if not args.no_cpu_baseline:
+    if cpu and not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         prec32, ks = None, (3, 10, 24)
         import oracle as O
@@ -360,6 +418,8 @@ def single_system(args, kind):
             prec32 = lambda v: O.poly_apply(prob.A, roots, v, np.float32)  # noqa: E731
             ks = (1, 2, 3)
         out["cpu_baseline"] = cpu_baseline(prob, last.cycles, m, prec32, ks)
+    del A64, A32, ws_ir, ws_64, P32, P64, b, x
+    torch.cuda.empty_cache()
     return out
 
 
@@ -666,7 +726,7 @@ def batch(args):
     A32 = A64.to_f32()
     m = args.restart or 50
     bt = G.Batch([s["A"].n for s in systems], restart=m)
-    bt.set_graph(bool(args.graph))
+    bt.set_graph(args.batch_graph != 0)
     ws = G.alloc_workspace(bt.workspace_bytes(), dev)
     if args.tiling:
         tr, gb = (int(v) for v in args.tiling.split(","))
@@ -702,6 +762,31 @@ def batch(args):
         sy = systems[s]
         r = np.linalg.norm(sy["B"] - host_csr(sy["A"]) @ Xh[offs[s]:offs[s + 1]], axis=0)
         worst = max(worst, float(np.max(r / np.linalg.norm(sy["B"], axis=0))))
+    # roofline of the block Gram-Schmidt pair on the matrix cores (block dots
+    # C = V^T W, then W -= V C) at the mean basis size of a cycle, timed with
+    # events on the stream it runs on: algorithmic bytes = the nblk basis
+    # blocks read twice, W read twice and written once (16 float32 columns per
+    # row), plus the float64 coefficients written and read back
+    nblk = (m + 1) // 2
+    wsr = G.alloc_workspace(bt.workspace_bytes(), dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    Vin = torch.rand(nblk * A.n * 16, generator=gen, device=dev) * 2 - 1
+    Wb = torch.rand(A.n * 16, generator=gen, device=dev) * 2 - 1
+    bt.bcgs_step(Vin, nblk, Wb, wsr)
+    torch.cuda.synchronize()
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bt.bcgs_step(Vin, nblk, Wb, wsr)
+    e1.record()
+    torch.cuda.synchronize()
+    step_us = e0.elapsed_time(e1) * 1e3 / reps
+    step_bytes = 2.0 * nblk * A.n * 64 + 3.0 * A.n * 64 + 2.0 * len(systems) * nblk * 256 * 8
+    gbs = step_bytes / (step_us * 1e-6) / 1e9
+    del Vin, Wb, wsr
+    torch.cuda.empty_cache()
     return {"metric": METRIC, "value": round(t, 4), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
             "ms_per_step": round(t * 1e3, 2), "higher_is_better": False, "scaling": "strong",
             "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
@@ -710,12 +795,17 @@ def batch(args):
                                    f"sides, rows={A.n}, nnz={A.nnz}, tol 1e-10 per column",
                        "systems": len(systems), "rhs": 16, "rows": A.n, "nnz": A.nnz, "restart": m},
             "rhs_solved_per_s": round(len(systems) * 16 / t, 2), "tiling": list(tiling[:2]),
-            "graph": bool(args.graph),
+            "graph": args.batch_graph != 0,
             "cycles_slowest_system": out["cycles"], "block_iters": out["block_iters"],
             "max_rel_res": out["max_rel_res"], "sampled_host_rel_res": worst,
             "fp64_batched_s": round(t64, 4), "ir_speedup_vs_fp64": round(t64 / t, 3),
             "fp64_cycles_slowest_system": out64["cycles"], "fp64_block_iters": out64["block_iters"],
-            "fp64_max_rel_res": out64["max_rel_res"]}
+            "fp64_max_rel_res": out64["max_rel_res"],
+            "roofline": {"kernel": "block Gram-Schmidt pair (bdots + bgemm)", "bound": "hbm",
+                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "avg_launch_us": round(step_us, 2), "bytes_per_launch": round(step_bytes),
+                         "basis_blocks": nblk}}
 
 
 def predictor(args):
@@ -793,10 +883,14 @@ def main():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="default workload: the headline line only, without the other configs' records")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run three plain copies of MIB MiB first (counter scale factor)")
     ap.add_argument("--persistent", type=int, default=-1,
                     help="one single-block kernel per restart cycle (1), off (0), or -1: on for n <= 1024")
+    ap.add_argument("--batch-graph", type=int, default=1,
+                    help="batch: replay each restart cycle as a hipGraph (1, default) or launch eagerly (0)")
     ap.add_argument("--graph", type=int, default=0,
                     help="replay each restart cycle as a hipGraph (no per-kernel events then)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -828,6 +922,20 @@ def main():
         out = bjac_leg(args)
     elif args.workload == "restart":
         out = restart_sweep(args)
+    elif args.workload == "laplace3d" and not args.no_configs and not args.grid and not args.restart:
+        # the headline (3D Laplacian 150^3) with the other configs' IR-vs-float64
+        # records beside it, each measured in this run
+        out = single_system(args, "laplace3d")
+        out["configs"] = {}
+        for key, fn in (("laplace2d_64", lambda: single_system(args, "laplace2d", steps=5, warmup=2,
+                                                                breakdown=False, extras=False, cpu=False)),
+                        ("convdiff_2500", lambda: single_system(args, "convdiff", steps=1, warmup=1,
+                                                                 breakdown=False, extras=False, cpu=False)),
+                        ("batch_256x16", lambda: batch(args))):
+            rec = fn()
+            out["configs"][key] = {k: v for k, v in rec.items()
+                                   if k not in ("metric", "n_gpus", "higher_is_better", "scaling",
+                                                "vs_baseline", "data")}
     else:
         out = single_system(args, args.workload)
     print(json.dumps(out), flush=True)
