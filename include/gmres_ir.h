@@ -45,6 +45,9 @@ typedef enum {
   GMR_STAGNATED = 2,         /* no residual decrease over `stagnation_cycles` restarts */
   GMR_LOSS_OF_ACCURACY = 3,  /* GMR_FLAG_STOP_ON_LOSS: the implicit residual met tol, the
                                 explicit one did not (§V-F); x = last iterate             */
+  GMR_SYSTEMS_FAILED = 4,    /* batched solves: some systems stopped on an error and were
+                                frozen at their last iterate, every other one finished;
+                                batch_system_status() tells which                        */
   GMR_ERR_INVALID = -1,      /* bad argument (null pointer, size, dtype mismatch, ...)   */
   GMR_ERR_HIP = -2,          /* a HIP call failed                                        */
   GMR_ERR_WORKSPACE = -3,    /* workspace smaller than gmres_workspace_bytes()           */
@@ -370,6 +373,17 @@ gmr_status batch_gmres_ir_solve(gmr_batch* b, const gmr_csr* A64, const gmr_csr*
                                 double* X, const float* Z, double tol, int32_t max_cycles, void* ws,
                                 size_t ws_bytes, gmr_batch_result* res, int32_t* sys_cycles,
                                 double* sys_rel_res, void* stream);
+
+/* Per-system outcome of the last batch_gmres_ir_solve / batch_gmres_solve on
+ * this batch, into the host array out (nsys entries): GMR_OK (every column
+ * reached tol), GMR_NOT_CONVERGED (max_cycles reached) or GMR_ERR_NONFINITE
+ * (the system's start block could not be orthonormalised: its random
+ * replacement columns were themselves dependent or not finite).  A system that
+ * fails is frozen at its iterate of that cycle and leaves the tile table; the
+ * others go on, and the solve returns GMR_SYSTEMS_FAILED when they all
+ * converged, with max_rel_res over the systems that did not fail.
+ * GMR_ERR_INVALID before any solve. */
+gmr_status batch_system_status(const gmr_batch* b, int32_t* out);
 
 /* The same solve with the whole inner block GMRES(m) in float64 (block
  * Gram-Schmidt on the float64 matrix cores): plain restarted block GMRES, the

@@ -452,9 +452,12 @@ class Batch:
                                                 float(tol), int(max_cycles), _ptr(ws), ws.numel(), C.byref(res),
                                                 cp, rp, _stream(B.device))
         check(status)
+        sys_status = np.zeros(self.nsys, dtype=np.int32)
+        check(lib().batch_system_status(self._h, sys_status.ctypes.data_as(C.c_void_p)))
         return {"status": res.status, "status_name": _capi.STATUS.get(res.status, str(res.status)),
                 "cycles": res.cycles, "block_iters": res.block_iters, "max_rel_res": res.max_rel_res,
-                "seconds": res.seconds, "sys_cycles": cyc, "sys_rel_res": rel.reshape(self.nsys, 16)}
+                "seconds": res.seconds, "sys_cycles": cyc, "sys_rel_res": rel.reshape(self.nsys, 16),
+                "sys_status": sys_status}
 
     def bcgs_step(self, Vin: torch.Tensor, nblk: int, W: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
         Cout = torch.empty((self.nsys, nblk, 16, 16), dtype=torch.float64, device=W.device)

@@ -15,7 +15,8 @@ GMR_FLAG_GRAPH = 1
 GMR_FLAG_PERSISTENT = 2
 GMR_FLAG_STOP_ON_LOSS = 4
 GMR_FLAG_HALF_BASIS = 8
-STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", 3: "GMR_LOSS_OF_ACCURACY", -1: "GMR_ERR_INVALID",
+STATUS = {0: "GMR_OK", 1: "GMR_NOT_CONVERGED", 2: "GMR_STAGNATED", 3: "GMR_LOSS_OF_ACCURACY",
+          4: "GMR_SYSTEMS_FAILED", -1: "GMR_ERR_INVALID",
           -2: "GMR_ERR_HIP", -3: "GMR_ERR_WORKSPACE", -4: "GMR_ERR_NONFINITE",
           -5: "GMR_ERR_UNSUPPORTED"}
 PROF = {"none": 0, "spmv": 1, "cgs_dots": 2, "cgs_update_dots": 3, "cgs_update_norm": 4,
@@ -27,8 +28,9 @@ EXPORTED = ["gmres_workspace_bytes", "spmv", "cgs2_orth", "cgs2_orth_noalloc", "
             "gmres_ir_solve", "gmres_f32prec_solve", "gmres_fd_workspace_bytes", "gmres_fd_solve", "csr_values_to_f32", "gmr_hessenberg_eigvals", "gmr_harmonic_ritz", "gmr_leja_order",
             "gmr_last_error", "batch_create", "batch_destroy", "batch_workspace_bytes",
             "batch_set_tiling", "batch_set_graph", "batch_get_tiling", "batch_autotune", "batch_gmres_ir_solve", "batch_gmres_solve",
-            "batch_bcgs_step", "mlp_param_count", "mlp_workspace_bytes", "mlp_forward",
-            "mlp_loss_grad", "mlp_adam_step", "matrix_stats"]
+            "batch_bcgs_step", "batch_system_status", "mlp_param_count", "mlp_workspace_bytes", "mlp_forward",
+            "mlp_loss_grad", "mlp_adam_step", "matrix_stats", "matrix_features_workspace_bytes",
+            "matrix_features"]
 
 
 class gmr_csr(C.Structure):
@@ -140,6 +142,8 @@ def load() -> C.CDLL:
     lib.batch_gmres_solve.restype = st
     lib.batch_bcgs_step.argtypes = [P, P, C.c_int32, P, P, P, C.c_size_t, P]
     lib.batch_bcgs_step.restype = st
+    lib.batch_system_status.argtypes = [P, P]
+    lib.batch_system_status.restype = st
     lib.mlp_param_count.argtypes = []
     lib.mlp_param_count.restype = C.c_int32
     lib.mlp_workspace_bytes.argtypes = [C.c_int32]
@@ -152,6 +156,10 @@ def load() -> C.CDLL:
     lib.mlp_adam_step.restype = st
     lib.matrix_stats.argtypes = [C.POINTER(gmr_csr), P, P, C.c_size_t, P]
     lib.matrix_stats.restype = st
+    lib.matrix_features_workspace_bytes.argtypes = [C.c_int32, C.c_int32]
+    lib.matrix_features_workspace_bytes.restype = C.c_size_t
+    lib.matrix_features.argtypes = [C.POINTER(gmr_csr), P, P, P, C.c_size_t, P]
+    lib.matrix_features.restype = st
     lib.gmr_last_error.argtypes = []
     lib.gmr_last_error.restype = C.c_char_p
     _lib = lib

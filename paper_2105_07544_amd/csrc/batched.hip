@@ -65,16 +65,88 @@ template <> struct Mx<double> {
 struct BTile { int sys, r0, nr, pad; };
 struct BSys { int row_off, n, tile_start, tile_count; };
 struct BState {
-  int active;      // some column still above the tolerance
+  int active;      // some column still above the tolerance (0 once the system failed)
   int cycle_done;  // the current cycle ended (after a block breakdown)
   int kblk;        // block columns completed in the current cycle
-  int failed;      // the start block could not be formed
+  int failed;      // the start block could not be formed: the system is frozen
   int brk;         // the current block column broke down: it is the cycle's last
   int pad;
 };
+// The state array has nsys + 1 entries: entry nsys is an idle system that is
+// never active.  Tiles past the current table's end belong to it, so a launch
+// of a fixed grid runs whatever the table holds and the rest exit at once.
 
 // A system whose block step is in progress.
 __device__ __forceinline__ bool running(const BState& s) { return s.active && !s.cycle_done && !s.brk; }
+
+// ---------------------------------------------------------------------------
+// Tile table of the active systems, built on the device at the start of every
+// restart cycle, so that a captured cycle replays with the table its cycle
+// needs (the same table an eager cycle builds, hence the same bits).  Tiles
+// have tile_rows rows, halved (to multiples of 16, down to min_rows) while the
+// active systems give fewer than `fill` tiles; system s owns tiles
+// [tile_start, tile_start + tile_count) in system order.  Entries from the
+// table's end up to `grid` (the fixed launch grid) are idle tiles of system
+// nsys.  A table longer than `grid` (excluded by the bound the host puts on
+// `grid`) sets failed on the idle system instead.  One block of kBlock threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void btiles_kernel(int nsys, BSys* __restrict__ sys, BState* st,
+                                                        int tile_rows, int min_rows, int fill, int grid,
+                                                        BTile* __restrict__ tiles) {
+  __shared__ int s_part[kBlock];
+  __shared__ int s_total;
+  const int t = threadIdx.x;
+  const int per = (nsys + kBlock - 1) / kBlock;  // a contiguous share of systems per thread
+  const int s0 = min(nsys, t * per);
+  const int s1 = min(nsys, s0 + per);
+  int tr = tile_rows;
+  int total = 0;
+  for (;;) {
+    int c = 0;
+    for (int s = s0; s < s1; ++s)
+      if (st[s].active) c += (sys[s].n + tr - 1) / tr;
+    s_part[t] = c;
+    __syncthreads();
+    if (t == 0) {
+      int sum = 0;
+      for (int i = 0; i < kBlock; ++i) sum += s_part[i];
+      s_total = sum;
+    }
+    __syncthreads();
+    total = s_total;
+    __syncthreads();
+    if (tr > min_rows && total < fill) tr = max(min_rows, tr / 2 / 16 * 16);
+    else break;
+  }
+  if (total > grid) {
+    if (t == 0) st[nsys].failed = 1;
+    return;
+  }
+  int c = 0;
+  for (int s = s0; s < s1; ++s)
+    if (st[s].active) c += (sys[s].n + tr - 1) / tr;
+  s_part[t] = c;
+  __syncthreads();
+  if (t == 0) {  // exclusive scan of the per-thread counts
+    int acc = 0;
+    for (int i = 0; i < kBlock; ++i) {
+      const int v = s_part[i];
+      s_part[i] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  int at = s_part[t];
+  for (int s = s0; s < s1; ++s) {
+    const int n = sys[s].n;
+    const int cnt = st[s].active ? (n + tr - 1) / tr : 0;
+    sys[s].tile_start = at;
+    sys[s].tile_count = cnt;
+    for (int i = 0; i < cnt; ++i) tiles[at + i] = BTile{s, sys[s].row_off + i * tr, min(tr, n - i * tr), 0};
+    at += cnt;
+  }
+  for (int i = total + t; i < grid; i += kBlock) tiles[i] = BTile{nsys, 0, 0, 0};
+}
 
 // ---------------------------------------------------------------------------
 // SpMM in the inner precision: Y = A X for the tiles of running systems.  16 lanes per
@@ -670,9 +742,10 @@ __global__ __launch_bounds__(kBlock) void bchol_kernel(BState* st, const double*
   const int c = e % P;
   if (mask) {
     if (mode == kCholStart) {
-      if (e == 0) {
+      if (e == 0) {  // the system is frozen at its current iterate; the others go on
         st[s].cycle_done = 1;
         st[s].failed = 1;
+        st[s].active = 0;
       }
     } else {
       double* Rb = Rbrk + (size_t)s * PP;
@@ -975,6 +1048,7 @@ struct gmr_batch {
   std::vector<BTile> tiles;
   int max_tiles = 0;  // tile count at the smallest tile size (workspace sizing)
   bool graph = false; // replay each restart cycle as a captured hipGraph
+  std::vector<int32_t> sys_status;  // per system, gmr_status of the last solve
 };
 
 namespace {
@@ -1059,7 +1133,7 @@ BLayout layout(const gmr_batch* b, size_t elt) {
   const size_t ns = b->nsys;
   L.tiles = take((size_t)b->max_tiles * sizeof(BTile));
   L.sys = take(ns * sizeof(BSys));
-  L.st = take(ns * sizeof(BState));
+  L.st = take((ns + 1) * sizeof(BState));
   L.gam = take(ns * P * 8);
   L.bnorm = take(ns * P * 8);
   L.dep = take(ns * 4);
@@ -1089,8 +1163,9 @@ struct BRun {
   BLayout L;
   char* base;
   hipStream_t s;
+  int grid = 0;  // fixed launch grid over a device-built table (0: the host table)
   template <class T> T* at(size_t off) const { return (T*)(base + off); }
-  int ntiles() const { return (int)b->tiles.size(); }
+  int ntiles() const { return grid > 0 ? grid : (int)b->tiles.size(); }
 };
 
 gmr_status launch_check(const char* what) {
@@ -1273,6 +1348,13 @@ gmr_status batch_set_graph(gmr_batch* b, int32_t on) {
   return GMR_OK;
 }
 
+gmr_status batch_system_status(const gmr_batch* b, int32_t* out) {
+  if (!b || !out) return gmr::fail(GMR_ERR_INVALID, "batch_system_status: null pointer");
+  if ((int)b->sys_status.size() != b->nsys) return gmr::fail(GMR_ERR_INVALID, "batch_system_status: no solve yet");
+  std::copy(b->sys_status.begin(), b->sys_status.end(), out);
+  return GMR_OK;
+}
+
 gmr_status batch_get_tiling(const gmr_batch* b, int32_t* tile_rows, int32_t* group_blocks) {
   if (!b || !tile_rows || !group_blocks) return gmr::fail(GMR_ERR_INVALID, "batch_get_tiling: null pointer");
   *tile_rows = b->tile_rows;
@@ -1315,9 +1397,15 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
   }
   const int ns = b->nsys;
   const int m = b->m;
+  // the host table supplies the systems' row ranges; the device rebuilds the
+  // tile list of the active systems at the start of every cycle
   fill_tiles(b, b->tile_rows, std::vector<char>(ns, 1));
-  int nt = R.ntiles();
   BT(upload_tables(R));
+  // Fixed grid of every tile launch.  No device-built table is longer: tiles
+  // are halved only while there are fewer than kFillTiles of them, and one
+  // halving at most triples a system's tile count.
+  R.grid = std::min(b->max_tiles, std::max(count_tiles(b, b->tile_rows), 3 * kFillTiles));
+  const int nt = R.ntiles();
   BTile* tl = R.at<BTile>(R.L.tiles);
   BSys* sy = R.at<BSys>(R.L.sys);
   BState* st = R.at<BState>(R.L.st);
@@ -1332,9 +1420,15 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
   double* C1d = R.at<double>(R.L.C1d);
   double* C2d = R.at<double>(R.L.C2d);
   T* Cf = R.at<T>(R.L.Cf);
-  std::vector<BState> hst(ns);
+  std::vector<BState> hst(ns + 1);
   for (auto& h : hst) h = BState{1, 0, 0, 0, 0, 0};
-  BH(hipMemcpyAsync(st, hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
+  hst[ns] = BState{0, 0, 0, 0, 0, 0};  // the idle system of the unused tiles
+  BH(hipMemcpyAsync(st, hst.data(), (ns + 1) * sizeof(BState), hipMemcpyHostToDevice, R.s));
+  auto tile_table = [&]() -> gmr_status {
+    btiles_kernel<<<1, kBlock, 0, R.s>>>(ns, sy, st, b->tile_rows, kMinTileRows, kFillTiles, R.grid, tl);
+    return launch_check("btiles_kernel");
+  };
+  BT(tile_table());
   // ||B|| per column, then the residual of the initial X
   bresidual_kernel<<<nt, kBlock, 0, R.s>>>(tl, nullptr, A64->row_ptr, A64->col_idx, (const double*)A64->val,
                                            nullptr, B, R64, rpart);
@@ -1353,6 +1447,7 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
   // residual; the same launches with the same arguments every cycle, so it
   // can be captured once and replayed.
   auto enqueue_cycle = [&]() -> gmr_status {
+    BT(tile_table());  // the systems still active after the last residual
     // --- start block: W = R/gamma, dependent columns from Z, Cholesky QR twice
     bcycle_reset_kernel<<<(ns + 63) / 64, 64, 0, R.s>>>(ns, st);
     bstart_kernel<T><<<nt, kBlock, 0, R.s>>>(tl, st, R64, gam, W);
@@ -1405,48 +1500,33 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
   int total_cycles = 0;
   int64_t block_iters = 0;
   gmr_status status = GMR_NOT_CONVERGED;
+  int failed = 0;
   for (int cyc = 0;; ++cyc) {
-    BH(hipMemcpyAsync(hst.data(), st, ns * sizeof(BState), hipMemcpyDeviceToHost, R.s));
+    BH(hipMemcpyAsync(hst.data(), st, (ns + 1) * sizeof(BState), hipMemcpyDeviceToHost, R.s));
     BH(hipStreamSynchronize(R.s));
-    int active = 0, failed = 0;
+    if (hst[ns].failed) {
+      status = gmr::fail(GMR_ERR_HIP, nm + ": internal error, the tile table outgrew its launch grid");
+      break;
+    }
+    int active = 0;
+    failed = 0;
     for (int s = 0; s < ns; ++s) {
-      if (hst[s].failed) ++failed;
+      if (hst[s].failed) ++failed;  // frozen (its start block could not be formed); the others go on
       else if (hst[s].active) ++active;
     }
     if (cyc > 0)
       for (int s = 0; s < ns; ++s)
         if (hst[s].kblk > 0) block_iters += hst[s].kblk;
-    if (failed) {
-      status = GMR_ERR_NONFINITE;
-      gmr::fail(GMR_ERR_NONFINITE, nm + ": a start block could not be orthonormalised");
-      break;
-    }
     if (active == 0) {
-      status = GMR_OK;
+      status = failed ? GMR_SYSTEMS_FAILED : GMR_OK;
       break;
     }
     if (cyc >= max_cycles) break;
     for (int s = 0; s < ns; ++s)
       if (hst[s].active) ++cycles[s];
     ++total_cycles;
-    if (!b->graph) {
-      // launches of this cycle cover the active systems only; when those give
-      // too few tiles to fill the GPU, the tiles are made smaller (a captured
-      // graph keeps the full table instead)
-      std::vector<char> use(ns);
-      for (int s = 0; s < ns; ++s) use[s] = hst[s].active && !hst[s].failed;
-      auto ntiles_at = [&](int tr) {
-        int t = 0;
-        for (int s = 0; s < ns; ++s)
-          if (use[s]) t += (b->sys_rows[s] + tr - 1) / tr;
-        return t;
-      };
-      int tr = b->tile_rows;
-      while (tr > kMinTileRows && ntiles_at(tr) < kFillTiles) tr = std::max(kMinTileRows, tr / 2 / 16 * 16);
-      fill_tiles(b, tr, use);
-      nt = R.ntiles();
-      BT(upload_tables(R));
-    }
+    // every launch of the cycle covers the device-built table of the systems
+    // still active, with smaller tiles when those are too few to fill the GPU
     if (b->graph) {
       if (!graph.g) BT(capture_graph(R.s, &graph.g, enqueue_cycle));
       BH(hipGraphLaunch(graph.g, R.s));
@@ -1455,16 +1535,25 @@ gmr_status solve_impl(const char* name, gmr_batch* b, const gmr_csr* A64, const 
     }
   }
   BH(hipStreamSynchronize(R.s));
-  fill_tiles(b, b->tile_rows, std::vector<char>(ns, 1));  // the full table again
+  if (status < 0) return status;
+  BH(hipMemcpy(hst.data(), st, (ns + 1) * sizeof(BState), hipMemcpyDeviceToHost));
   std::vector<double> hg(ns * P), hb(ns * P);
   BH(hipMemcpy(hg.data(), gam, ns * P * 8, hipMemcpyDeviceToHost));
   BH(hipMemcpy(hb.data(), bnorm, ns * P * 8, hipMemcpyDeviceToHost));
   double worst = 0.0;
-  for (int i = 0; i < ns * P; ++i) {
-    const double r = hb[i] > 0.0 ? hg[i] / hb[i] : 0.0;
-    worst = std::max(worst, r);
-    if (sys_rel_res) sys_rel_res[i] = r;
+  b->sys_status.assign(ns, GMR_OK);
+  for (int s = 0; s < ns; ++s) {
+    b->sys_status[s] = hst[s].failed ? GMR_ERR_NONFINITE : (hst[s].active ? GMR_NOT_CONVERGED : GMR_OK);
+    for (int c = 0; c < P; ++c) {
+      const int i = s * P + c;
+      const double r = hb[i] > 0.0 ? hg[i] / hb[i] : 0.0;
+      if (!hst[s].failed) worst = std::max(worst, r);
+      if (sys_rel_res) sys_rel_res[i] = r;
+    }
   }
+  if (status == GMR_SYSTEMS_FAILED)
+    gmr::fail(GMR_SYSTEMS_FAILED, nm + ": " + std::to_string(failed) +
+                                      " system(s) stopped: a start block could not be orthonormalised");
   if (sys_cycles)
     for (int s = 0; s < ns; ++s) sys_cycles[s] = cycles[s];
   const auto t1 = std::chrono::steady_clock::now();
@@ -1590,12 +1679,17 @@ gmr_status batch_bcgs_step(gmr_batch* b, const float* Vin, int32_t nblk, float* 
   BH(hipMemcpyAsync(R.at<BState>(R.L.st), hst.data(), ns * sizeof(BState), hipMemcpyHostToDevice, R.s));
   fill_tiles(b, b->tile_rows, std::vector<char>(ns, 1));
   BT(upload_tables(R));
-  BH(hipMemcpyAsync(R.at<float>(R.L.V), Vin, (size_t)nblk * R.L.vstride * 4, hipMemcpyDeviceToDevice, R.s));
-  BT(dots<float>(R, R.at<float>(R.L.V), nblk, W, R.at<double>(R.L.Cd), R.at<float>(R.L.Cf)));
-  for (int s = 0; s < ns; ++s)
-    BH(hipMemcpyAsync(C + (size_t)s * nblk * PP, R.at<double>(R.L.Cd) + (size_t)s * R.L.cstride,
-                      (size_t)nblk * PP * 8, hipMemcpyDeviceToDevice, R.s));
-  return gemm<float, kSub>(R, R.at<float>(R.L.V), nblk, R.at<float>(R.L.Cf), W);
+  // the kernels read the caller's blocks in place when they are aligned as
+  // the workspace basis is (256 bytes), a copy of them otherwise
+  const float* V = Vin;
+  if ((uintptr_t)Vin % 256 != 0) {
+    BH(hipMemcpyAsync(R.at<float>(R.L.V), Vin, (size_t)nblk * R.L.vstride * 4, hipMemcpyDeviceToDevice, R.s));
+    V = R.at<float>(R.L.V);
+  }
+  BT(dots<float>(R, V, nblk, W, R.at<double>(R.L.Cd), R.at<float>(R.L.Cf)));
+  BH(hipMemcpy2DAsync(C, (size_t)nblk * PP * 8, R.at<double>(R.L.Cd), R.L.cstride * 8, (size_t)nblk * PP * 8, ns,
+                      hipMemcpyDeviceToDevice, R.s));
+  return gemm<float, kSub>(R, V, nblk, R.at<float>(R.L.Cf), W);
 }
 
 }  // extern "C"

@@ -181,6 +181,14 @@ def test_batch_host_api_without_device():
     b.set_graph(True)
     b.set_graph(False)
     assert lib.batch_set_graph(None, 1) == -1
+    # per-system statuses exist only after a solve
+    st = np.zeros(3, dtype=np.int32)
+    assert lib.batch_system_status(b.handle, st.ctypes.data_as(C.c_void_p)) == -1
+    assert lib.batch_system_status(None, st.ctypes.data_as(C.c_void_p)) == -1
+    # the features' workspace query is host arithmetic
+    assert lib.matrix_features_workspace_bytes(1000, G.GMR_F64) > lib.matrix_features_workspace_bytes(1000, G.GMR_F32) > 0
+    assert lib.matrix_features_workspace_bytes(0, G.GMR_F64) == 0
+    assert lib.matrix_features_workspace_bytes(10, 5) == 0
     out = C.c_void_p()
     rows = np.array([10, 0], dtype=np.int32)
     assert lib.batch_create(2, rows.ctypes.data_as(C.c_void_p), 16, 8, C.byref(out)) == -1
