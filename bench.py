@@ -14,8 +14,10 @@ Other workloads (each prints its own line; the default line is the one above):
   laplace2d  2D Laplacian 64^2, GMRES(50)
   batch      256 convection-diffusion systems x 16 right-hand sides, batched
              block GMRES(50)-IR on the matrix cores
-  predictor  the learned parameter predictor: label, train on the GPU, and
-             compare held-out time to solution with the fixed (m=50, d=0, f32)
+  predictor  the learned parameter predictor: train on the GPU on the labelled
+             config-5 systems, then time held-out systems live with the
+             predicted (m, degree, precision) and with the fixed (50, 0, f32)
+  predictor-label  label config-5 training systems by branch and bound
   fd         GMRES-FD switch-point sweep on the 3D Laplacian 200^3 (b = ones):
              float32 GMRES(50) for s iterations, then float64 GMRES(50)
   prec32     polynomial degrees 10..70 on the same Laplacian: float64 GMRES with
@@ -808,40 +810,90 @@ def batch(args):
                          "basis_blocks": nblk}}
 
 
-def predictor(args):
+LABELS_FILE = os.path.join(ROOT, "paper_2105_07544_amd", "predictor_data", "config5_train.jsonl")
+
+
+def predictor_label(args):
+    """Labels training systems start .. start+count-1 of the config-5
+    distribution (seed 5) by branch and bound over the 40 combinations and
+    appends one JSON record per system to --label-out (default: the committed
+    training file)."""
+    import numpy as np
+
     import workloads as W
     from paper_2105_07544_amd import predictor as PR
 
-    ntr, nte = args.train, args.test
-    train = W.config5_systems(ntr, seed=5)
-    test = W.config5_systems(nte, seed=6)
-    v_tr = [W.uniform_pm1(10000 + i, s["A"].n) for i, s in enumerate(train)]
-    v_te = [W.uniform_pm1(20000 + i, s["A"].n) for i, s in enumerate(test)]
+    out_path = args.label_out or LABELS_FILE
+    systems = W.config5_systems(args.label_count, seed=5, start=args.label_start)
     t0 = time.perf_counter()
-    dtr = PR.build_dataset(train, v_tr, "cuda:0", log=log if args.verbose else None)
-    dte = PR.build_dataset(test, v_te, "cuda:0", log=log if args.verbose else None)
-    t_label = time.perf_counter() - t0
+    recs = []
+    wins = {}
+    for s in systems:
+        # combinations that won on the systems labelled so far go first (a
+        # tighter bound sooner); the label does not depend on the order
+        order = sorted(PR.COMBOS, key=lambda c: -wins.get(c, 0))
+        v0 = W.uniform_pm1(10000 + s["index"], s["A"].n)
+        t1 = time.perf_counter()
+        r = PR.label_system(s, v0, "cuda:0", base_cap_s=args.base_cap, order=order, log=log)
+        r["index"] = s["index"]
+        r["label_seconds"] = round(time.perf_counter() - t1, 3)
+        best = PR.COMBOS[int(np.argmin([np.inf if t is None else t for t in r["times"]]))]
+        wins[best] = wins.get(best, 0) + 1
+        recs.append(r)
+        with open(out_path, "a") as fh:
+            fh.write(json.dumps(r) + "\n")
+        log(f"bench: labelled system {s['index']} ({r['label_seconds']} s)")
+    return {"metric": "labelled config-5 training systems", "value": len(recs), "unit": "systems",
+            "start": args.label_start, "count": args.label_count, "seconds": round(time.perf_counter() - t0, 1),
+            "file": os.path.relpath(out_path, ROOT)}
+
+
+def predictor(args):
+    """Trains the network on the GPU on the labelled training systems, then
+    times held-out systems start .. start+count-1 (seed 6) live with the
+    predicted combination and with the fixed one (m = 50, d = 0, float32)."""
+    import numpy as np
+
+    import workloads as W
+    from paper_2105_07544_amd import predictor as PR
+
+    with open(args.labels or LABELS_FILE) as fh:
+        recs = [json.loads(line) for line in fh if line.strip()]
+    recs.sort(key=lambda r: r["index"])
+    dtr = PR.dataset_from_records(recs)
     mu, sd = dtr.X.mean(0), dtr.X.std(0) + 1e-6
     net = PR.Net(PR.init_params(23), mu, sd, "cuda:0")
     epochs = 400
     t0 = time.perf_counter()
     hist = net.train(dtr.X, dtr.labels, epochs=epochs, batch=64, lr=3e-3, order_seed=700)
     t_train = time.perf_counter() - t0
-    ev_tr, ev_te = PR.evaluate(net, dtr), PR.evaluate(net, dte)
-    ev_tr.pop("predictions")
-    ev_te.pop("predictions")
-    return {"metric": METRIC, "value": round(ev_te["total_pred"], 5), "unit": "s", "n_gpus": 1,
-            "steps": 1, "warmup": 0, "ms_per_step": round(ev_te["total_pred"] * 1e3, 3),
+    fit = PR.evaluate(net, dtr)
+    fit.pop("predictions")
+    test = W.config5_systems(args.test, seed=6, start=args.test_start)
+    rows = []
+    for s in test:
+        v0 = W.uniform_pm1(20000 + s["index"], s["A"].n)
+        r = PR.evaluate_system(net, s, v0, "cuda:0", base_cap_s=args.base_cap)
+        rows.append(r)
+        log(f"bench: held-out {s['index']} n={r['n']} {r['kind']} pred={tuple(r['predicted'])} "
+            f"{r['t_pred']:.4f}s fixed={r['t_fixed']:.4f}s")
+        if args.test_out:
+            with open(args.test_out, "a") as fh:
+                fh.write(json.dumps(r) + "\n")
+    live = PR.summarize_live(rows)
+    kinds = {k: sum(r["kind"] == k for r in recs) for k in ("convdiff", "laplace2d", "laplace3d")}
+    return {"metric": METRIC, "value": round(live["total_pred"], 5), "unit": "s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": round(live["total_pred"] * 1e3, 3),
             "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
-            "config": {"workload": f"learned (m, degree, precision) predictor: {ntr} training and {nte} "
-                                   "held-out systems (half upwind convection-diffusion, a quarter 2D and a "
-                                   "quarter 3D Laplacians), 40 combinations timed per system",
-                       "train": ntr, "test": nte},
-            "held_out": ev_te, "train_fit": ev_tr, "fixed_baseline_total_s": ev_te["total_base"],
-            "gain_vs_fixed": round(ev_te["total_base"] / ev_te["total_pred"], 3),
-            "label_seconds": round(t_label, 2),
-            "train_samples_per_s": round(epochs * ntr / t_train, 1),
+            "config": {"workload": (f"learned (m, degree, precision) predictor: trained on {len(recs)} labelled "
+                                    "systems (half upwind convection-diffusion, a quarter 2D and a quarter 3D "
+                                    "Laplacians; 2D side U{64..1024}, 3D side U{16..101}), held-out systems "
+                                    f"{args.test_start}..{args.test_start + args.test - 1} timed live"),
+                       "train": len(recs), "test": len(rows), "train_kinds": kinds,
+                       "grid_side_2d": [64, 1024], "grid_side_3d": [16, 101], "fixed_budget_s": args.base_cap},
+            "held_out": live, "gain_vs_fixed": live["gain_total"], "train_fit": fit,
+            "train_samples_per_s": round(epochs * len(recs) / t_train, 1),
             "loss_first_last": [hist[0], hist[-1]]}
 
 
@@ -868,12 +920,19 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="laplace3d",
-                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "fd", "prec32", "bjac",
-                             "restart"])
+                    choices=["laplace3d", "convdiff", "laplace2d", "batch", "predictor", "predictor-label", "fd",
+                             "prec32", "bjac", "restart"])
     ap.add_argument("--grid", type=int, default=0, help="grid side (0: the workload's own)")
     ap.add_argument("--restart", type=int, default=0, help="restart length (0: the workload's own)")
-    ap.add_argument("--train", type=int, default=192, help="predictor: training systems")
-    ap.add_argument("--test", type=int, default=64, help="predictor: held-out systems")
+    ap.add_argument("--test", type=int, default=32, help="predictor: held-out systems timed live")
+    ap.add_argument("--test-start", type=int, default=0, help="predictor: first held-out system")
+    ap.add_argument("--test-out", default="", help="predictor: append per-system held-out records here")
+    ap.add_argument("--labels", default="", help="predictor: labelled training file (default: the committed one)")
+    ap.add_argument("--label-start", type=int, default=0, help="predictor-label: first training system")
+    ap.add_argument("--label-count", type=int, default=8, help="predictor-label: systems to label")
+    ap.add_argument("--label-out", default="", help="predictor-label: output file (default: the committed one)")
+    ap.add_argument("--base-cap", type=float, default=4.0,
+                    help="predictor: time budget (s) of the fixed combination and of a predicted one")
     ap.add_argument("--fd-stride", type=int, default=0, help="fd: switch-point stride (0: 5 restarts)")
     ap.add_argument("--fd-max", type=int, default=0, help="fd: last switch point (0: float64 GMRES's count)")
     ap.add_argument("--degrees", default="10,20,30,40,50,60,70", help="prec32: polynomial degrees")
@@ -914,6 +973,8 @@ def main():
         out = batch(args)
     elif args.workload == "predictor":
         out = predictor(args)
+    elif args.workload == "predictor-label":
+        out = predictor_label(args)
     elif args.workload == "fd":
         out = fd_sweep(args)
     elif args.workload == "prec32":

@@ -433,6 +433,28 @@ gmr_status mlp_adam_step(float* params, const float* grad, float* m, float* v, i
  * 13 * 8 * (min(ceil(n/256), 1024) + 1) bytes.  Synchronous. */
 gmr_status matrix_stats(const gmr_csr* A, double* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Bytes of device workspace matrix_features needs for an n x n matrix of
+ * the given dtype (0 for bad arguments). */
+size_t matrix_features_workspace_bytes(int32_t n, int32_t dtype);
+
+/* The 16 predictor features of A into the host array out, in this order:
+ * log10 n; nonzeros per row; most nonzeros in a row; min and mean diagonal
+ * dominance |a_ii| / sum_{j!=i} |a_ij| (rows with off-diagonal entries; min is
+ * 10 when there are none) and the fraction of rows with dominance >= 1;
+ * Gershgorin min (a_ii - r_i), max (a_ii + r_i) and max r_i, each divided by
+ * max |a_ii|; ||A - A^T||_F / ||A||_F; std / |mean| of the diagonal; from an
+ * Arnoldi run of min(5, n) steps from the device vector v0 (n entries of A's
+ * dtype, need not be normalised; fewer steps after a lucky breakdown): max |theta| and
+ * min |theta| of its Ritz values over max |a_ii|, log10 of their ratio,
+ * max |Im theta| / max |theta| and h_{k+1,k} / max |theta|.  Non-finite values
+ * are replaced by 0, +1e6 or -1e6.  These are cheap estimates of what the
+ * paper's guidance for the restart length, the polynomial degree and the
+ * precision turns on (§V-B, §V-C, §V-E, §V-F): conditioning, normality and
+ * the spread of the spectrum.  Columns must ascend within a row.  ws: device,
+ * matrix_features_workspace_bytes(n, dtype) bytes.  Synchronous. */
+gmr_status matrix_features(const gmr_csr* A, const void* v0, double* out, void* ws, size_t ws_bytes,
+                           void* stream);
+
 const char* gmr_last_error(void);
 
 #ifdef __cplusplus

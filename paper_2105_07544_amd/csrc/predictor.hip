@@ -11,6 +11,7 @@
 // Adam runs element-wise.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -242,6 +243,55 @@ __global__ void stats_finish_kernel(int nparts, const double* __restrict__ part,
   }
   out[q] = v;
 }
+// Steps of the Arnoldi run whose Ritz values enter the features (at most n).
+constexpr int kArnoldiSteps = 5;
+
+// The 16 features from the 13 row statistics (matrix_stats order), the
+// (k+1) x k Hessenberg matrix H of the k-step Arnoldi run (column-major, ld k+1)
+// and the Ritz values theta (eigenvalues of its leading k x k block):
+//  0 log10 n            1 nonzeros per row        2 max nonzeros in a row
+//  3 min dominance      4 mean dominance          5 dominant-row fraction
+//  6-8 Gershgorin min (a_ii - r_i), max (a_ii + r_i), max r_i, each over max |a_ii|
+//  9 ||A - A^T||_F / ||A||_F                      10 std / |mean| of the diagonal
+// 11 max |theta|, 12 min |theta| (over max |a_ii|), 13 log10 of their ratio,
+// 14 max |Im theta| / max |theta|, 15 h_{k+1,k} / max |theta|.
+// Dominance is |a_ii| / sum_{j != i} |a_ij| over rows with off-diagonal
+// entries (10 when there are none).  Non-finite values become 0, +1e6, -1e6.
+inline void features_from(int n, int nnz, const double* s, int k, const double* H, const double* re,
+                          const double* im, double* f) {
+  const double maxd = std::max(s[7], 1e-300);
+  const double rows_off = std::max(s[3], 1.0);
+  const double mean_d = s[8] / n;
+  const double var_d = std::max(s[9] / n - mean_d * mean_d, 0.0);
+  double amax = 0.0, amin = INFINITY, imax = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double a = std::hypot(re[i], im[i]);
+    amax = std::max(amax, a);
+    amin = std::min(amin, a);
+    imax = std::max(imax, std::fabs(im[i]));
+  }
+  f[0] = std::log10((double)n);
+  f[1] = (double)nnz / n;
+  f[2] = s[10];
+  f[3] = s[3] > 0 ? s[1] : 10.0;
+  f[4] = s[0] / rows_off;
+  f[5] = s[2] / n;
+  f[6] = s[4] / maxd;
+  f[7] = s[5] / maxd;
+  f[8] = s[6] / maxd;
+  f[9] = std::sqrt(s[12] / std::max(s[11], 1e-300));
+  f[10] = std::sqrt(var_d) / std::max(std::fabs(mean_d), 1e-300);
+  f[11] = amax / maxd;
+  f[12] = amin / maxd;
+  f[13] = std::log10(amax / std::max(amin, 1e-300));
+  f[14] = imax / amax;
+  f[15] = H[(size_t)(k - 1) * (k + 1) + k] / amax;
+  for (int i = 0; i < 16; ++i) {
+    if (std::isnan(f[i])) f[i] = 0.0;
+    else if (std::isinf(f[i])) f[i] = f[i] > 0 ? 1e6 : -1e6;
+  }
+}
+
 }  // namespace feat
 }  // namespace gmr
 
@@ -321,6 +371,40 @@ gmr_status matrix_stats(const gmr_csr* A, double* out, void* ws, size_t ws_bytes
   if (hipMemcpyAsync(out, res, feat::NS * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return gmr::fail(GMR_ERR_HIP, "matrix_stats: copy failed");
+  return GMR_OK;
+}
+
+size_t matrix_features_workspace_bytes(int32_t n, int32_t dtype) {
+  if (n <= 0 || (dtype != GMR_F32 && dtype != GMR_F64)) return 0;
+  const gmr_params p{feat::kArnoldiSteps, 1e-10, 1, 0, 0, 0, 0};
+  const size_t arnoldi = gmres_workspace_bytes(n, &p, dtype, 0);
+  const size_t stats = (size_t)(std::min((n + kBlock - 1) / kBlock, 1024) + 1) * feat::NS * sizeof(double);
+  return std::max(arnoldi, stats);
+}
+
+gmr_status matrix_features(const gmr_csr* A, const void* v0, double* out, void* ws, size_t ws_bytes,
+                           void* stream) {
+  if (!A || !v0 || !out) return gmr::fail(GMR_ERR_INVALID, "matrix_features: null pointer");
+  if (A->n <= 0 || (A->dtype != GMR_F32 && A->dtype != GMR_F64))
+    return gmr::fail(GMR_ERR_INVALID, "matrix_features: bad matrix");
+  if (!ws || ws_bytes < matrix_features_workspace_bytes(A->n, A->dtype))
+    return gmr::fail(GMR_ERR_WORKSPACE, "matrix_features: workspace too small");
+  double st[feat::NS];
+  gmr_status rc = matrix_stats(A, st, ws, ws_bytes, stream);
+  if (rc != GMR_OK) return rc;
+  // the Arnoldi run of a degree-(steps-1) polynomial setup: its Hessenberg matrix
+  gmr_poly* P = nullptr;
+  rc = poly_prec_setup(A, std::min(feat::kArnoldiSteps, A->n) - 1, v0, ws, ws_bytes, &P, stream);
+  if (rc != GMR_OK) return rc;
+  const int k = poly_prec_degree(P) + 1;  // fewer steps after a lucky breakdown
+  std::vector<double> H((size_t)(k + 1) * k), Hk((size_t)k * k), re(k), im(k);
+  rc = poly_prec_hessenberg(P, H.data());
+  poly_prec_destroy(P);
+  if (rc != GMR_OK) return rc;
+  for (int c = 0; c < k; ++c)
+    for (int r = 0; r < k; ++r) Hk[(size_t)c * k + r] = H[(size_t)c * (k + 1) + r];
+  if ((rc = gmr_hessenberg_eigvals(k, Hk.data(), re.data(), im.data())) != GMR_OK) return rc;
+  feat::features_from(A->n, A->nnz, st, k, H.data(), re.data(), im.data(), out);
   return GMR_OK;
 }
 

@@ -6,10 +6,11 @@ GMRES-polynomial degree d in {0, 5, 10, 25, 40} and the inner precision
 fastest.  The paper gives rules of thumb for each choice (§V-B, §V-C, §V-E,
 §V-F); here a 16-64-64-11 MLP learns them from solver runs.
 
-* features: 11 row statistics from one GPU pass over A (``matrix_stats``) and
-  5 Ritz-value features from a 5-step Arnoldi run on the GPU;
-* labels: the measured time-to-solution of every (m, d, precision)
-  combination, the fastest one being the label;
+* features: the library call ``matrix_features`` (11 row statistics from one
+  GPU pass over A and 5 Ritz-value features of a 5-step Arnoldi run);
+* labels: the fastest (m, d, precision) combination by measured time to
+  1e-10, found by branch and bound (a combination is stopped once it has
+  spent more than the best time so far, which cannot change the argmin);
 * training: the library's forward, backward and Adam kernels;
 * solving: the predicted combination, with the fixed combination
   (m = 50, d = 0, float32) as the fallback when the predicted one does not
@@ -20,13 +21,13 @@ from __future__ import annotations
 import ctypes as C
 import math
 from dataclasses import dataclass
-from typing import List, Optional
+from typing import List
 
 import numpy as np
 import torch
 
 from . import DeviceCSR, GMR_F32, GMR_F64, alloc_workspace, gmres_ir_solve, gmres_solve, lib
-from . import hessenberg_eigvals, poly_prec_setup, workspace_bytes
+from . import poly_prec_setup, workspace_bytes
 from ._capi import check
 
 RESTARTS = (25, 50, 100, 200)
@@ -64,53 +65,15 @@ def matrix_stats(A: DeviceCSR) -> np.ndarray:
 
 
 def features(A: DeviceCSR, v0: torch.Tensor) -> np.ndarray:
-    """16 features of A; v0 is the start vector of the 5-step Arnoldi run."""
-    s = matrix_stats(A)
-    n, nnz = A.n, A.nnz
-    maxd = max(s[7], 1e-300)
-    rows_off = max(s[3], 1.0)
-    mean_d = s[8] / n
-    var_d = max(s[9] / n - mean_d * mean_d, 0.0)
-    P = poly_prec_setup(A, 4, v0)
-    H = P.hessenberg()
-    k = H.shape[1]
-    theta = hessenberg_eigvals(H[:k, :k])
-    amax = float(np.max(np.abs(theta)))
-    amin = float(np.min(np.abs(theta)))
-    f = [
-        math.log10(n),
-        nnz / n,
-        s[10],
-        s[1] if s[3] > 0 else 10.0,
-        s[0] / rows_off,
-        s[2] / n,
-        s[4] / maxd,
-        s[5] / maxd,
-        s[6] / maxd,
-        math.sqrt(s[12] / max(s[11], 1e-300)),
-        math.sqrt(var_d) / max(abs(mean_d), 1e-300),
-        amax / maxd,
-        amin / maxd,
-        math.log10(amax / max(amin, 1e-300)),
-        float(np.max(np.abs(theta.imag))) / amax,
-        float(H[k, k - 1]) / amax if H.shape[0] > k else 0.0,
-    ]
-    return np.nan_to_num(np.array(f, dtype=np.float64), nan=0.0, posinf=1e6, neginf=-1e6)
-
-
-def solve_combo(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, combo, v0: torch.Tensor,
-                max_iters: int = 20000):
-    """Time one (m, d, precision) solve from x0 = 0; the polynomial setup is
-    outside the timed solve (as in §V-C).  Returns (seconds or inf, result)."""
-    m, d, prec = combo
-    if prec == "f32":
-        P = poly_prec_setup(A32, d, v0.float()) if d > 0 else None
-        x, r = gmres_ir_solve(A64, A32, b, restart=m, tol=1e-10, max_iters=max_iters,
-                              stagnation_cycles=20, P=P)
-    else:
-        P = poly_prec_setup(A64, d, v0.double()) if d > 0 else None
-        x, r = gmres_solve(A64, b, restart=m, tol=1e-10, max_iters=max_iters, P=P)
-    return (r.seconds if r.converged else math.inf), r
+    """The 16 features of A (library call matrix_features); v0 (A's dtype) is
+    the start vector of the 5-step Arnoldi run."""
+    out = np.zeros(NFEAT)
+    dt = GMR_F64 if A.val.dtype == torch.float64 else GMR_F32
+    ws = alloc_workspace(lib().matrix_features_workspace_bytes(A.n, dt), A.device)
+    st = A.struct()
+    check(lib().matrix_features(C.byref(st), _ptr(v0), out.ctypes.data_as(C.c_void_p), _ptr(ws), ws.numel(),
+                                _stream(A.device)))
+    return out
 
 
 @dataclass
@@ -137,28 +100,6 @@ def labels_from_times(times: np.ndarray) -> np.ndarray:
 def device_system(sysd, device="cuda"):
     A64 = DeviceCSR.from_host(sysd["A"], device)
     return A64, A64.to_f32(), torch.from_numpy(sysd["b"]).to(device)
-
-
-def build_dataset(systems, start_vectors, device="cuda", max_iters: int = 6000, log=None) -> Dataset:
-    """Features and the measured time of all 40 combinations for each system
-    (an attempt that does not converge within max_iters, or stagnates, is
-    recorded as inf, with the time it spent)."""
-    X = np.zeros((len(systems), NFEAT))
-    T = np.full((len(systems), len(COMBOS)), math.inf)
-    S = np.zeros((len(systems), len(COMBOS)))
-    for i, s in enumerate(systems):
-        A64, A32, b = device_system(s, device)
-        v0 = torch.from_numpy(start_vectors[i]).to(device)
-        X[i] = features(A64, v0.double())
-        solve_combo(A64, A32, b, BASELINE, v0, max_iters=200)  # warm-up
-        for c in COMBOS:
-            t, r = solve_combo(A64, A32, b, c, v0, max_iters=max_iters)
-            T[i, combo_index(c)] = t
-            S[i, combo_index(c)] = r.seconds
-        if log:
-            log(f"system {i}: n={s['A'].n} best={COMBOS[int(np.argmin(T[i]))]} "
-                f"t={np.min(T[i]):.4f}s baseline={T[i, combo_index(BASELINE)]:.4f}s")
-    return Dataset(X, T, S, labels_from_times(T))
 
 
 class Net:
@@ -246,3 +187,128 @@ def evaluate(net: Net, ds: Dataset):
                 fallbacks=fallbacks, systems=int(ok.sum()),
                 accuracy=float(np.mean([combo_index(c) == int(np.argmin(ds.times[i])) for i, c in enumerate(pred)])),
                 predictions=[list(c) for c in pred])
+
+
+# ---------------------------------------------------------------------------
+# Labelling at scale: branch and bound over the 40 combinations
+# ---------------------------------------------------------------------------
+def _chunked_solve(A64, A32, b, combo, v0, cap_s: float, max_iters: int):
+    """Solve from x0 = 0 with one combination, in calls of 1, 2, 4, ... restart
+    cycles, each continuing from the previous call's iterate (a restarted
+    solver's cycles depend only on the iterate, so the sequence is the same as
+    one uninterrupted solve; each call adds one residual product).  Stops once
+    the summed solve time exceeds cap_s.  The polynomial setup is outside the
+    timing (§V-C).  Returns (seconds, converged, iterations, capped)."""
+    m, d, prec = combo
+    if prec == "f32":
+        P = poly_prec_setup(A32, d, v0.float()) if d > 0 else None
+    else:
+        P = poly_prec_setup(A64, d, v0.double()) if d > 0 else None
+    x = torch.zeros_like(b)
+    ws = alloc_workspace(workspace_bytes(A64.n, m, GMR_F32 if prec == "f32" else GMR_F64, d > 0), b.device)
+    spent, iters, chunk = 0.0, 0, 1
+    while True:
+        left = max_iters - iters
+        if prec == "f32":
+            _, r = gmres_ir_solve(A64, A32, b, x, restart=m, tol=1e-10, max_iters=left, max_cycles=chunk,
+                                  P=P, ws=ws)
+        else:
+            _, r = gmres_solve(A64, b, x, restart=m, tol=1e-10, max_iters=left, max_cycles=chunk, P=P, ws=ws)
+        spent += r.seconds
+        iters += r.iters
+        if r.converged:
+            return spent, True, iters, False
+        if r.status_name not in ("GMR_NOT_CONVERGED",) or iters >= max_iters:
+            return spent, False, iters, False
+        if spent > cap_s:
+            return spent, False, iters, True
+        chunk *= 2
+
+
+def label_system(sysd, v0: np.ndarray, device="cuda", base_cap_s: float = 4.0, max_iters: int = 100000,
+                 order=None, log=None) -> dict:
+    """Features and the measured time to 1e-10 of the 40 combinations of one
+    system, by branch and bound: the fixed combination first (capped at
+    base_cap_s), then the others in the given order, each stopped as soon as
+    its time exceeds the best time so far.  A stopped combination cannot be the
+    fastest, so the label (the argmin) is exact; its entry in `times` is inf and
+    `bounds` holds the time it had spent (a lower bound of its time)."""
+    A64, A32, b = device_system(sysd, device)
+    v = torch.from_numpy(v0).to(device)
+    feats = features(A64, v.double())
+    _chunked_solve(A64, A32, b, BASELINE, v, 0.0, 50)  # warm-up of the kernels at this size
+    times = np.full(len(COMBOS), math.inf)
+    bounds = np.zeros(len(COMBOS))
+    iters = np.zeros(len(COMBOS), dtype=np.int64)
+    capped = np.zeros(len(COMBOS), dtype=bool)
+    kb = combo_index(BASELINE)
+    t, ok, it, cp = _chunked_solve(A64, A32, b, BASELINE, v, base_cap_s, max_iters)
+    bounds[kb], iters[kb], capped[kb] = t, it, cp
+    if ok:
+        times[kb] = t
+    best = t if ok else base_cap_s
+    for c in (order or COMBOS):
+        k = combo_index(c)
+        if k == kb:
+            continue
+        t, ok, it, cp = _chunked_solve(A64, A32, b, c, v, best, max_iters)
+        bounds[k], iters[k], capped[k] = t, it, cp
+        if ok and t < best:
+            times[k] = t
+            best = t
+        elif ok:
+            times[k] = t
+    out = dict(n=int(sysd["A"].n), nnz=int(sysd["A"].nnz), kind=sysd["kind"], N=int(sysd["N"]),
+               features=feats.tolist(), times=[None if not np.isfinite(x) else float(x) for x in times],
+               bounds=bounds.tolist(), iters=iters.tolist(), capped=capped.tolist())
+    if log:
+        kbest = int(np.argmin(times))
+        log(f"n={out['n']} {out['kind']} best={COMBOS[kbest]} {times[kbest]:.4f}s "
+            f"fixed={times[kb]:.4f}s labelled in {bounds.sum():.1f}s")
+    return out
+
+
+def dataset_from_records(records) -> Dataset:
+    """Dataset of labelled systems (label_system records)."""
+    X = np.array([r["features"] for r in records], dtype=np.float64)
+    T = np.array([[math.inf if t is None else t for t in r["times"]] for r in records])
+    S = np.array([r["bounds"] for r in records])
+    return Dataset(X, T, S, labels_from_times(T))
+
+
+def evaluate_system(net: "Net", sysd, v0: np.ndarray, device="cuda", base_cap_s: float = 4.0,
+                    max_iters: int = 100000) -> dict:
+    """Time to 1e-10 of one unseen system with the predicted combination and
+    with the fixed one, each given the same budget base_cap_s; when the
+    predicted one does not converge within it, the fixed combination runs
+    after it and both times are charged (the fallback)."""
+    A64, A32, b = device_system(sysd, device)
+    v = torch.from_numpy(v0).to(device)
+    f = features(A64, v.double())
+    pred = net.predict(f[None, :])[0]
+    _chunked_solve(A64, A32, b, BASELINE, v, 0.0, 50)  # warm-up of the kernels at this size
+    tb, okb, itb, _ = _chunked_solve(A64, A32, b, BASELINE, v, base_cap_s, max_iters)
+    if pred == BASELINE:
+        tp, okp, itp, fb = tb, okb, itb, False
+    else:
+        tp, okp, itp, _ = _chunked_solve(A64, A32, b, pred, v, base_cap_s, max_iters)
+        fb = not okp
+        if fb:
+            tp, okp = tp + tb, okb
+    return dict(index=int(sysd.get("index", -1)), n=int(sysd["A"].n), kind=sysd["kind"], N=int(sysd["N"]),
+                predicted=list(pred), t_pred=tp, pred_converged=bool(okp), fallback=fb,
+                t_fixed=tb, fixed_converged=bool(okb), iters_pred=int(itp), iters_fixed=int(itb))
+
+
+def summarize_live(rows) -> dict:
+    """Totals and the geometric mean of time(predicted, fallback included) /
+    time(fixed) over the systems the fixed combination solves within its
+    budget; the others are counted apart."""
+    ok = [r for r in rows if r["fixed_converged"]]
+    tp = np.array([r["t_pred"] for r in ok])
+    tb = np.array([r["t_fixed"] for r in ok])
+    return dict(systems=len(rows), fixed_solves=len(ok), total_pred=float(tp.sum()), total_fixed=float(tb.sum()),
+                gain_total=float(tb.sum() / tp.sum()) if len(ok) else None,
+                geomean_ratio=float(np.exp(np.mean(np.log(tp / tb)))) if len(ok) else None,
+                fallbacks=int(sum(r["fallback"] for r in rows)),
+                fixed_failed_pred_solved=int(sum((not r["fixed_converged"]) and r["pred_converged"] for r in rows)))

@@ -555,3 +555,42 @@ def check_block_arnoldi_breakdown():
 
 
 ALL_CHECKS.append(check_block_arnoldi_breakdown)
+
+
+# --- O9b predictor features -------------------------------------------------------
+def check_features_hand_matrix():
+    # A = [[2, -1, 0], [0, 3, -1], [-1, 0, 4]], worked by hand: diagonal 2, 3, 4,
+    # off-diagonal sums 1, 1, 1, dominance 2, 3, 4, ||A||_F^2 = 32,
+    # ||A - A^T||_F^2 = 6, diagonal mean 3 and std sqrt(2/3).  Three Arnoldi
+    # steps from a generic vector span R^3, so the Ritz values are A's
+    # eigenvalues and the run ends with h_{4,3} = 0.
+    import oracle.features as F
+    D = np.array([[2.0, -1.0, 0.0], [0.0, 3.0, -1.0], [-1.0, 0.0, 4.0]])
+    A = dense_csr(D)
+    f = F.features(A, np.array([1.0, 0.3, -0.7]))
+    lam = np.linalg.eigvals(D)
+    want = [np.log10(3), 2.0, 2.0, 2.0, 3.0, 1.0, 1 / 4, 5 / 4, 1 / 4, np.sqrt(6 / 32),
+            np.sqrt(2 / 3) / 3, np.abs(lam).max() / 4, np.abs(lam).min() / 4,
+            np.log10(np.abs(lam).max() / np.abs(lam).min()), np.abs(lam.imag).max() / np.abs(lam).max(), 0.0]
+    assert np.allclose(f, want, rtol=1e-10, atol=1e-12), np.c_[f, want]
+
+
+def check_features_laplacian_closed_form():
+    # 2D Laplacian 4/-1 on N^2: corners dominate with ratio 2, edges 4/3, the
+    # interior exactly 1; Gershgorin discs [0, 8] scaled by the diagonal 4;
+    # symmetric (nonsymmetry 0, real Ritz values) with a constant diagonal;
+    # the Ritz values lie inside the closed-form spectrum
+    import oracle.features as F
+    N = 12
+    A = W.laplace2d(N)
+    f = F.features(A, rng(70).standard_normal(A.n))
+    n = N * N
+    mean_dom = (4 * 2.0 + 4 * (N - 2) * 4 / 3 + (N - 2) ** 2 * 1.0) / n
+    assert np.allclose(f[:11], [np.log10(n), (5 * n - 4 * N) / n, 5, 1.0, mean_dom, 1.0, 0.0, 2.0, 1.0, 0.0, 0.0],
+                       rtol=1e-12, atol=1e-12), f[:11]
+    lam = W.laplacian_eigs_closed_form(N, 2)
+    assert lam.min() / 4 * (1 - 1e-12) <= f[12] <= f[11] <= lam.max() / 4 * (1 + 1e-12)
+    assert f[14] == 0.0 and f[15] > 0
+
+
+ALL_CHECKS += [check_features_hand_matrix, check_features_laplacian_closed_form]

@@ -7,10 +7,11 @@ import oracle.krylov as K
 import oracle.poly as P
 import oracle.block as O_blk
 import oracle.precond as O_pre
+import oracle.features as O_feat
 import pins
 
 
-def _patch(monkeypatch, name, fn, modules=(oracle, K, P, O_pre, O_blk)):
+def _patch(monkeypatch, name, fn, modules=(oracle, K, P, O_pre, O_blk, O_feat)):
     for m in modules:
         if hasattr(m, name):
             monkeypatch.setattr(m, name, fn)
@@ -183,6 +184,15 @@ def block_arnoldi_zero_r(A, V0, m, dt):
     return blocks, H[: (k + 1) * p, : k * p], k
 
 
+def row_stats_with_diagonal(A):
+    # mistake: the diagonal counted in the off-diagonal sum r_i
+    D = A.to_dense()
+    d = np.diag(D).copy()
+    r = np.array([sum(abs(D[i, j]) for j in range(A.n) if D[i, j] != 0.0) for i in range(A.n)])
+    return dict(d=d, r=r, nnz_row=np.diff(A.row_ptr), fro2=float((D * D).sum()),
+                skew2=float(((D - D.T) ** 2).sum()))
+
+
 MUTATIONS = {
     "spmv_drop_last": ("spmv", spmv_drop_last),
     "spmv_row_index": ("spmv", spmv_row_index),
@@ -201,6 +211,7 @@ MUTATIONS = {
     "half_store_identity": ("half_store", half_store_identity),
     "leja_by_modulus": ("leja_order", leja_by_modulus),
     "block_arnoldi_zero_r": ("block_arnoldi", block_arnoldi_zero_r),
+    "features_diag_in_offdiag_sum": ("row_stats", row_stats_with_diagonal),
 }
 
 FAST_CHECKS = [c for c in pins.ALL_CHECKS if c.__name__ not in

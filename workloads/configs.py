@@ -128,13 +128,15 @@ def stack_rows(blocks) -> np.ndarray:
     return np.ascontiguousarray(np.concatenate(blocks, axis=0))
 
 
-def config5_systems(count: int, seed: int = 5, side2d=(24, 128), side3d=(8, 24)):
-    """Systems for the parameter predictor: half upwind convection-diffusion
-    (diffusion 10^U(-3,0), random wind angle), a quarter 2D and a quarter 3D
-    Laplacians.  System i draws from stream seed ^ (i + 1): draw 1 the kind,
-    draw 2 the grid side, draws 3-4 diffusion and wind angle, then x_true."""
+def config5_systems(count: int, seed: int = 5, side2d=(64, 1024), side3d=(16, 101), start: int = 0):
+    """Systems start .. start+count-1 for the parameter predictor: half upwind
+    convection-diffusion (diffusion 10^U(-3,0), random wind angle), a quarter
+    2D and a quarter 3D Laplacians; 2D grid side U{64..1024}, 3D side
+    U{16..101} (n of the same range).  System i draws from stream
+    seed ^ (i + 1): draw 1 the kind, draw 2 the grid side, draws 3-4 diffusion
+    and wind angle, then x_true."""
     out = []
-    for i in range(count):
+    for i in range(start, start + count):
         s = seed ^ (i + 1)
         u = uniform01(s, 4)
         kind = "convdiff" if u[0] < 0.5 else ("laplace2d" if u[0] < 0.75 else "laplace3d")
@@ -153,5 +155,5 @@ def config5_systems(count: int, seed: int = 5, side2d=(24, 128), side3d=(8, 24))
                 A = convdiff2d(N, eps, lambda x, y, p=phi: (np.cos(p), np.sin(p)))
                 meta = dict(kind=kind, N=N, eps=eps, phi=phi)
         x_true = uniform_pm1(s, A.n, 4)
-        out.append(dict(A=A, b=host_matvec(A, x_true), x_true=x_true, seed=s, **meta))
+        out.append(dict(A=A, b=host_matvec(A, x_true), x_true=x_true, seed=s, index=i, **meta))
     return out
