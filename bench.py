@@ -273,8 +273,9 @@ def single_system(args, kind, steps=None, warmup=None, breakdown=True, extras=Tr
                if prob.x_true is not None else None)
         return rel, fwd
 
-    # small systems run each restart cycle as one single-block kernel
-    pers = (args.persistent == 1) or (args.persistent < 0 and prob.A.n <= 1024)
+    # small and mid-size systems run each restart cycle as one launch: one
+    # block up to n = 1024, a cooperative multi-block grid up to n = 6144
+    pers = (args.persistent == 1) or (args.persistent < 0 and prob.A.n <= 6144)
 
     def ir(prof="none", g=None):
         x.zero_()
@@ -947,7 +948,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run three plain copies of MIB MiB first (counter scale factor)")
     ap.add_argument("--persistent", type=int, default=-1,
-                    help="one single-block kernel per restart cycle (1), off (0), or -1: on for n <= 1024")
+                    help="one launch per restart cycle (1), off (0), or -1: on for n <= 6144")
     ap.add_argument("--batch-graph", type=int, default=1,
                     help="batch: replay each restart cycle as a hipGraph (1, default) or launch eagerly (0)")
     ap.add_argument("--graph", type=int, default=0,

@@ -87,13 +87,16 @@ typedef struct {
  * restart (ignored while profiling).  The solve then runs on a library-owned
  * non-blocking stream after `stream` has drained; results are the same bits. */
 #define GMR_FLAG_GRAPH 1
-/* gmr_params.flags: for a small system (n <= 1024) without a polynomial,
- * run each whole restart cycle (cast, inner iterations, update, residual) as
- * one kernel of one block, with block barriers instead of kernel boundaries:
- * one launch per cycle instead of about eight per iteration (2-4x faster at
- * n ~ 150, break-even at n ~ 1000).  Ignored when it does not apply (larger n,
- * polynomial, profiling, GMR_FLAG_GRAPH); the arithmetic is the same, summed
- * in a different grouping. */
+/* gmr_params.flags: for a system of n <= 6144 without a polynomial, run each
+ * whole restart cycle (cast, inner iterations, update, residual) as one launch
+ * instead of about eight per inner iteration: up to n = 1024 one block with
+ * block barriers (2-4x faster at n ~ 150), above it a cooperative launch of
+ * ceil(n / 256) co-resident blocks with grid barriers where the
+ * multi-kernel cycle has kernel boundaries (four per iteration).  Ignored when
+ * it does not apply (larger n, polynomial, profiling, GMR_FLAG_GRAPH, a device
+ * that cannot hold the grid); the arithmetic is the same, summed in a
+ * different grouping, and repeatable bit for bit.  A grid barrier that does
+ * not complete within about a second ends the solve with GMR_ERR_HIP. */
 #define GMR_FLAG_PERSISTENT 2
 /* gmr_params.flags: plain GMRES (gmres_solve, gmres_f32prec_solve, the float64
  * phase of gmres_fd_solve) ends with GMR_LOSS_OF_ACCURACY at the first restart

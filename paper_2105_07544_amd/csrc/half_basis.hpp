@@ -34,11 +34,10 @@ __global__ __launch_bounds__(kBlock) void spmv_hb_kernel(int n, const int* __res
                                                          half_t* __restrict__ vout, float* __restrict__ y,
                                                          const int* __restrict__ done) {
   __shared__ __align__(16) float s_prod[SpmvCfg<float>::kChunk];
-  if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
   const float s = float(*scale);
   float acc[kSpmvRpt];
-  spmv_rows<float, true>(n, r0, rp, ci, val, x, s, s_prod, acc);
+  if (!spmv_rows<float, true>(n, r0, rp, ci, val, x, s, s_prod, acc, done)) return;
 #pragma unroll
   for (int i = 0; i < kSpmvRpt; ++i) {
     const int r = r0 + threadIdx.x + i * kBlock;

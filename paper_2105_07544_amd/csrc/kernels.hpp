@@ -63,6 +63,14 @@ struct Status {
   int done;           // the cycle ended early (implicit convergence or breakdown)
   int breakdown;      // h_{j+1,j} was zero (lucky breakdown)
   int nonfinite;      // NaN/Inf met in the small dense problem
+  int barrier_timeout;  // a grid barrier of the cooperative cycle gave up waiting
+  int pad;
+};
+
+// State of the grid barrier of the cooperative cycle (zeroed before each launch).
+struct GridBarrier {
+  unsigned int count;  // blocks arrived at the current barrier
+  unsigned int gen;    // barriers completed
 };
 
 struct CycleState {
@@ -140,17 +148,25 @@ __device__ __forceinline__ void store_quad(T* dst, const T (&p)[4]) {
 // block reads, so no per-entry masking is needed.  The
 // row bounds come straight from global memory: the block's first and last
 // (uniform, scalar loads) and each thread's own, with no LDS staging and no
-// barrier before the nonzero loads are issued.
+// barrier before the nonzero loads are issued.  A non-null `done` flag is read
+// together with those uniform row bounds (one round trip for both instead of
+// one before the other); when it is set the whole block returns false and the
+// caller skips its epilogue.
 template <class T, bool SCALED, int CH = SpmvCfg<T>::kChunk>
-__device__ __forceinline__ void spmv_rows(int n, int r0, const int* __restrict__ rp,
+__device__ __forceinline__ bool spmv_rows(int n, int r0, const int* __restrict__ rp,
                                           const int* __restrict__ ci, const T* __restrict__ val,
-                                          const T* __restrict__ x, T s, T* s_prod, T (&acc)[kSpmvRpt]) {
+                                          const T* __restrict__ x, T s, T* s_prod, T (&acc)[kSpmvRpt],
+                                          const int* __restrict__ done = nullptr) {
   constexpr int Q = CH / (4 * kBlock);  // quads per thread per pass
   const int t = threadIdx.x;
   const int nr = min(kSpmvRows, n - r0);
+  // without a flag the load reads row_ptr[0] (0 by the CSR convention), so
+  // the four uniform loads have no branch between them
+  const int* flag = done ? done : rp;
   const int k0 = rp[r0];
   const int k1 = rp[r0 + nr];
   const int nnz = rp[n];
+  if (*flag != 0 && done) return false;
   int rs[kSpmvRpt], re[kSpmvRpt];
 #pragma unroll
   for (int i = 0; i < kSpmvRpt; ++i) {
@@ -203,6 +219,7 @@ __device__ __forceinline__ void spmv_rows(int n, int r0, const int* __restrict__
     }
     __syncthreads();
   }
+  return true;
 }
 
 // y = A x.  When `scale` is non-null the input is x * (*scale) and, when `vout`
@@ -217,12 +234,11 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n, const int* __restri
                                                       T* __restrict__ vout, T* __restrict__ y,
                                                       const int* __restrict__ done) {
   __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
-  if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
   T acc[kSpmvRpt];
   if (scale) {
     const T s = T(*scale);
-    spmv_rows<T, true>(n, r0, rp, ci, val, x, s, s_prod, acc);
+    if (!spmv_rows<T, true>(n, r0, rp, ci, val, x, s, s_prod, acc, done)) return;
     if (vout) {
 #pragma unroll
       for (int i = 0; i < kSpmvRpt; ++i) {
@@ -231,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int n, const int* __restri
       }
     }
   } else {
-    spmv_rows<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, acc);
+    if (!spmv_rows<T, false>(n, r0, rp, ci, val, x, T(1), s_prod, acc, done)) return;
   }
 #pragma unroll
   for (int i = 0; i < kSpmvRpt; ++i) {
@@ -912,10 +928,9 @@ __global__ __launch_bounds__(kBlock) void poly_real_kernel(int n, const int* __r
                                                            T* __restrict__ Y, T* __restrict__ Pn,
                                                            const int* __restrict__ done) {
   __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
-  if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
   T ap[kSpmvRpt];
-  spmv_rows<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, ap);
+  if (!spmv_rows<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, ap, done)) return;
 #pragma unroll
   for (int i = 0; i < kSpmvRpt; ++i) {
     const int r = r0 + threadIdx.x + i * kBlock;
@@ -946,10 +961,9 @@ __global__ __launch_bounds__(kBlock) void poly_pair1_kernel(int n, const int* __
                                                             T* __restrict__ Y, T* __restrict__ Tt,
                                                             const int* __restrict__ done) {
   __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
-  if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
   T t[kSpmvRpt];
-  spmv_rows<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, t);
+  if (!spmv_rows<T, false>(n, r0, rp, ci, val, P, T(1), s_prod, t, done)) return;
 #pragma unroll
   for (int i = 0; i < kSpmvRpt; ++i) {
     const int r = r0 + threadIdx.x + i * kBlock;
@@ -972,10 +986,9 @@ __global__ __launch_bounds__(kBlock) void poly_pair2_kernel(int n, const int* __
                                                             T* __restrict__ Pn,
                                                             const int* __restrict__ done) {
   __shared__ __align__(16) T s_prod[SpmvCfg<T>::kChunk];
-  if (done && *done) return;
   const int r0 = xcd_remap(blockIdx.x, gridDim.x) * kSpmvRows;
   T at[kSpmvRpt];
-  spmv_rows<T, false>(n, r0, rp, ci, val, Tt, T(1), s_prod, at);
+  if (!spmv_rows<T, false>(n, r0, rp, ci, val, Tt, T(1), s_prod, at, done)) return;
 #pragma unroll
   for (int i = 0; i < kSpmvRpt; ++i) {
     const int r = r0 + threadIdx.x + i * kBlock;
@@ -1108,6 +1121,214 @@ __global__ __launch_bounds__(kBlock) void small_cycle_kernel(
     const double g = sqrt(sq);
     st->gamma = g;
     st->inv_gamma = 1.0 / g;
+  }
+}
+
+// ===========================================================================
+// Cooperative multi-block cycle for mid-size systems
+// ===========================================================================
+// Above kSmallMaxN one block cannot hide the latency of a whole cycle, while
+// the multi-kernel cycle pays about eight launches per iteration.  Here a
+// cooperative launch of G co-resident blocks runs the whole restart cycle, with
+// grid barriers where the multi-kernel cycle has kernel boundaries that carry
+// data between blocks: four per inner iteration (five beyond 64 basis
+// columns, where the first update and the second dots run apart).
+// Above about 6000 rows the grid barriers cost more than the launches they
+// replace (n = 9216: 34.7 ms per GMRES-IR solve against 29.3 for the
+// multi-kernel cycle).
+constexpr int kCoopMaxN = 6144;
+constexpr int kCoopMaxBlocks = 64;
+// Column partials of consecutive CGS passes alternate between two halves of
+// each column's pitch, so a block may write the next pass's partials while a
+// slower one still reads the previous pass's.
+constexpr int kCoopAlt = kPartPitch / 2;
+static_assert(kCoopMaxBlocks <= kCoopAlt, "partials of one pass must fit half a column pitch");
+
+// Grid-wide barrier on device-scope vector atomics: thread 0 of each block
+// publishes the block's writes (release), counts itself in, and the last one
+// resets the count and advances the generation that the others wait on
+// (acquire).  All blocks of a cooperative launch are resident, so every wait
+// ends; a wait that has not ended after about a second gives up, flags
+// barrier_timeout and lets the kernel run to its end, so a broken barrier
+// cannot hang the device.
+__device__ __forceinline__ void grid_sync(GridBarrier* bar, unsigned int& gen, Status* st) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int g = gen;
+    const unsigned int arrived =
+        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int spins = 0;
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1 << 24)) {
+          __hip_atomic_store(&st->barrier_timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  gen += 1;
+  __syncthreads();
+}
+
+// Column sums of the G block partials of a CGS pass, added in block order:
+// every block keeps them (in the inner precision) in LDS, block 0 also stores
+// the float64 sums for the Givens step.
+template <class T>
+__device__ __forceinline__ void coop_take_cols(int j, int G, const double* __restrict__ part, double* out_d,
+                                               T* s_out) {
+  for (int c = threadIdx.x; c < j; c += kBlock) {
+    double s = 0.0;
+    for (int b = 0; b < G; ++b) s += part[(size_t)c * kPartPitch + b];
+    s_out[c] = T(s);
+    if (blockIdx.x == 0) out_d[c] = s;
+  }
+}
+
+// 1 / beta of the latest column from the norm partials, as the Givens step
+// computes it (same partial sum, same roundings), so every block has it.
+template <class T>
+__device__ __forceinline__ double coop_inv_beta(int G, const double* __restrict__ part) {
+  __shared__ double s_ib;
+  const double s = sum_partials(G, part);
+  if (threadIdx.x == 0) s_ib = 1.0 / double(T(sqrt(double(T(s)))));
+  __syncthreads();
+  return s_ib;
+}
+
+// One whole restart cycle on G = gridDim.x co-resident blocks (cooperative
+// launch): the cast of r, up to mc inner iterations, the solution update and
+// the next residual with its norm.  Per iteration: the SpMV of the rows of the
+// block's 512-row groups | barrier | CGS2 dots | barrier | update + dots |
+// barrier | update + norm | barrier; every block then takes 1 / beta from the
+// norm partials and goes on with the next SpMV while block 0 runs the float64
+// Givens step, whose flags the others read after the next barrier.  Sums of
+// block partials are added in block order (deterministic).
+template <class TI, class TO>
+__global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
+    int n, const int* __restrict__ rp, const int* __restrict__ ci, const TI* __restrict__ vin,
+    const int* __restrict__ rpo, const int* __restrict__ cio, const TO* __restrict__ vout,
+    const TO* __restrict__ b, TO* __restrict__ x, TO* __restrict__ r, TI* V,
+    int64_t ldv, TI* w0, TI* w1, CycleState cs, double* partial, GridBarrier* bar, int mc, double stop_rel,
+    double thresh) {
+  // passes of 1024 entries keep the block's LDS (with the CGS bodies') within 160 KB
+  constexpr int kChunk = 1024;
+  __shared__ __align__(16) TI s_pi[kChunk];
+  __shared__ __align__(16) TO s_po[kChunk];
+  __shared__ TI s_h[kMaxCols];
+  __shared__ int s_done;
+  Status* st = cs.st;
+  const int G = gridDim.x;
+  double* partA = partial;
+  double* partB = partial + kCoopAlt;
+  unsigned int gen = 0;
+  start_cycle_body<TO, TI>(n, r, w0, partA, st);
+  grid_sync(bar, gen, st);
+  double inv_beta;
+  {
+    __shared__ double s_ib0;
+    const double s = sum_partials(G, partA);
+    if (threadIdx.x == 0) s_ib0 = 1.0 / sqrt(double(TI(s)));
+    __syncthreads();
+    inv_beta = s_ib0;
+  }
+  if (blockIdx.x == 0) finish_start_cycle_body<TI>(G, partA, cs, stop_rel);
+  TI* wc = w0;  // the current w (the unnormalised v_j)
+  TI* wn = w1;  // A v_j
+  for (int j = 0; j < mc; ++j) {
+    TI* vj = V + (size_t)j * ldv;
+    const TI s = TI(inv_beta);
+    for (int r0 = blockIdx.x * kSpmvRows; r0 < n; r0 += G * kSpmvRows) {
+      TI acc[kSpmvRpt];
+      spmv_rows<TI, true, kChunk>(n, r0, rp, ci, vin, wc, s, s_pi, acc);
+#pragma unroll
+      for (int i = 0; i < kSpmvRpt; ++i) {
+        const int row = r0 + threadIdx.x + i * kBlock;
+        if (row < n) {
+          vj[row] = wc[row] * s;
+          wn[row] = acc[i];
+        }
+      }
+    }
+    grid_sync(bar, gen, st);
+    // block 0's Givens step of the previous column is complete: the cycle may be over
+    if (threadIdx.x == 0) s_done = st->done || st->barrier_timeout;
+    __syncthreads();
+    if (s_done) break;
+    const int jj = j + 1;  // basis columns
+    if (jj <= 8) cgs_dots_body<TI, 8, 1>(n, jj, V, ldv, wn, partA, nullptr);
+    else if (jj <= 16) cgs_dots_body<TI, 16, 1>(n, jj, V, ldv, wn, partA, nullptr);
+    else if (jj <= 32) cgs_dots_body<TI, 32, 1>(n, jj, V, ldv, wn, partA, nullptr);
+    else if (jj <= 64) cgs_dots_body<TI, 64, 1>(n, jj, V, ldv, wn, partA, nullptr);
+    else if (jj <= 256) cgs_dots_body<TI, 64, 4>(n, jj, V, ldv, wn, partA, nullptr);
+    else cgs_dots_body<TI, 64, 8>(n, jj, V, ldv, wn, partA, nullptr);
+    grid_sync(bar, gen, st);
+    coop_take_cols<TI>(jj, G, partA, cs.h1d, s_h);
+    __syncthreads();
+    if (jj <= 8) cgs_update_dots_body<TI, 8>(n, jj, V, ldv, s_h, wn, partB, nullptr);
+    else if (jj <= 16) cgs_update_dots_body<TI, 16>(n, jj, V, ldv, s_h, wn, partB, nullptr);
+    else if (jj <= 32) cgs_update_dots_body<TI, 32>(n, jj, V, ldv, s_h, wn, partB, nullptr);
+    else if (jj <= 64) cgs_update_dots_body<TI, 64>(n, jj, V, ldv, s_h, wn, partB, nullptr);
+    else {
+      // the update walks rows four per thread, the dots a row per lane: the
+      // rows change hands between blocks, so a grid barrier separates them
+      cgs_update_body<TI>(n, jj, V, ldv, s_h, wn, nullptr);
+      grid_sync(bar, gen, st);
+      if (jj <= 256) cgs_dots_body<TI, 64, 4>(n, jj, V, ldv, wn, partB, nullptr);
+      else cgs_dots_body<TI, 64, 8>(n, jj, V, ldv, wn, partB, nullptr);
+    }
+    grid_sync(bar, gen, st);
+    coop_take_cols<TI>(jj, G, partB, cs.h2d, s_h);
+    __syncthreads();
+    cgs_update_norm_body<TI>(n, jj, V, ldv, s_h, wn, partA, nullptr);
+    grid_sync(bar, gen, st);
+    inv_beta = coop_inv_beta<TI>(G, partA);
+    if (blockIdx.x == 0) finish_norm_body<TI, kTailGivens>(G, partA, cs, jj, mc - 1, thresh, nullptr, nullptr);
+    TI* t = wc;
+    wc = wn;
+    wn = t;
+  }
+  // y and k of block 0's last Givens step
+  grid_sync(bar, gen, st);
+  solution_update_body<TI, TO>(n, V, ldv, cs.y, st, nullptr, x);
+  grid_sync(bar, gen, st);
+  double sq = 0.0;
+  for (int r0 = blockIdx.x * kSpmvRows; r0 < n; r0 += G * kSpmvRows) {
+    TO acc[kSpmvRpt];
+    spmv_rows<TO, false, kChunk>(n, r0, rpo, cio, vout, x, TO(1), s_po, acc);
+#pragma unroll
+    for (int i = 0; i < kSpmvRpt; ++i) {
+      const int row = r0 + threadIdx.x + i * kBlock;
+      if (row < n) {
+        const TO rv = b[row] - acc[i];
+        r[row] = rv;
+        sq += double(rv) * double(rv);
+      }
+    }
+  }
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) partA[blockIdx.x] = sq;
+  grid_sync(bar, gen, st);
+  if (blockIdx.x == 0) {
+    const double g = sqrt(sum_partials(G, partA));
+    if (threadIdx.x == 0) {
+      st->gamma = g;
+      st->inv_gamma = 1.0 / g;
+    }
+  }
+}
+
+__global__ void coop_reset_kernel(GridBarrier* bar, Status* st) {
+  if (threadIdx.x == 0) {
+    bar->count = 0;
+    bar->gen = 0;
+    st->barrier_timeout = 0;
   }
 }
 

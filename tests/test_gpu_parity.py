@@ -492,3 +492,49 @@ def test_persistent_cycle_matches_multikernel(n_side, restart):
         # a second persistent run is bitwise the same (deterministic block sums)
         xc, rc = f(restart=restart, tol=1e-10, max_iters=20000, persistent=True)
         assert np.array_equal(host(xb), host(xc)) and rb.history == rc.history
+
+
+# ---------------------------------------------------------------------------
+# Cooperative multi-block cycle (1024 < n <= 6144)
+# ---------------------------------------------------------------------------
+def test_cooperative_cycle_config1_against_oracle():
+    say("cooperative cycle, 2D Laplacian 64x64")
+    p = W.config1_laplace2d(N=64)
+    A = dev(p.A)
+    A32 = A.to_f32()
+    x1, r1 = G.gmres_solve(A, t64(p.b), restart=50, tol=1e-10, max_iters=20000, persistent=True)
+    ref = O.gmres(p.A, p.b, np.zeros(p.A.n), 50, 1e-10, 20000)
+    say("f64", r1.iters, r1.cycles, r1.rel_res, "oracle", ref.iters)
+    assert r1.converged and abs(r1.iters - ref.iters) <= max(2, 0.02 * ref.iters)
+    assert np.linalg.norm(p.b - O.spmv(p.A, host(x1))) / np.linalg.norm(p.b) <= 1e-10
+    x2, r2 = G.gmres_ir_solve(A, A32, t64(p.b), restart=50, tol=1e-10, max_iters=20000, persistent=True)
+    ref2 = O.gmres_ir(p.A, p.b, np.zeros(p.A.n), 50, 1e-10, 20000)
+    say("ir", r2.iters, r2.cycles, r2.rel_res, "oracle", ref2.cycles)
+    assert r2.converged and r2.iters % 50 == 0
+    assert abs(r2.cycles - ref2.cycles) <= max(1, 0.1 * ref2.cycles)
+    assert np.linalg.norm(p.b - O.spmv(p.A, host(x2))) / np.linalg.norm(p.b) <= 1e-10
+    h, hr = np.array(r2.history), np.array(ref2.history)
+    k = min(len(h), len(hr))
+    assert np.all(np.abs(np.log10(h[:k]) - np.log10(hr[:k])) < 1.0)
+
+
+@pytest.mark.parametrize("n_side,restart", [(33, 50), (70, 80), (78, 30), (50, 20)])
+def test_cooperative_cycle_matches_multikernel(n_side, restart):
+    # 1089 rows (five blocks, ragged last one), 4900 rows with restart beyond
+    # the fused 64-column pass, 6084 rows (24 blocks, near the largest n),
+    # 2500 rows (ten blocks, a ragged SpMV group)
+    say("cooperative vs multi-kernel", n_side, restart)
+    A_h = W.convdiff2d(n_side, 0.05, lambda x, y: (np.cos(2 * x), np.sin(3 * y)))
+    b_h = W.uniform_pm1(78, A_h.n)
+    A = dev(A_h)
+    A32 = A.to_f32()
+    for f in (lambda **k: G.gmres_solve(A, t64(b_h), **k), lambda **k: G.gmres_ir_solve(A, A32, t64(b_h), **k)):
+        xa, ra = f(restart=restart, tol=1e-10, max_iters=40000)
+        xb, rb = f(restart=restart, tol=1e-10, max_iters=40000, persistent=True)
+        say(ra.iters, rb.iters, ra.rel_res, rb.rel_res)
+        assert ra.converged and rb.converged
+        assert abs(ra.iters - rb.iters) <= max(2, 0.05 * ra.iters)
+        assert np.linalg.norm(b_h - O.spmv(A_h, host(xb))) / np.linalg.norm(b_h) <= 1e-10
+        # deterministic: block partials are added in block order
+        xc, rc = f(restart=restart, tol=1e-10, max_iters=40000, persistent=True)
+        assert np.array_equal(host(xb), host(xc)) and rb.history == rc.history
