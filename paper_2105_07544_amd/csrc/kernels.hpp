@@ -226,7 +226,7 @@ __device__ __forceinline__ bool spmv_rows(int n, int r0, const int* __restrict__
 // is non-null, that scaled input is also written to vout for the block's rows
 // (this is how v_{j+1} = w / h_{j+1,j} is stored without a separate pass).
 template <class T>
-__global__ __launch_bounds__(kBlock) void spmv_kernel(int n, const int* __restrict__ rp,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_kernel(int n, const int* __restrict__ rp,
                                                       const int* __restrict__ ci,
                                                       const T* __restrict__ val,
                                                       const T* __restrict__ x,
@@ -921,7 +921,7 @@ __global__ __launch_bounds__(kBlock) void cast_f64_f32_kernel(int64_t n, const d
 
 // Real root: Y (+)= c P ; P_next = P - c (A P)  (first: Y is not read).
 template <class T, bool FIRST>
-__global__ __launch_bounds__(kBlock) void poly_real_kernel(int n, const int* __restrict__ rp,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void poly_real_kernel(int n, const int* __restrict__ rp,
                                                            const int* __restrict__ ci,
                                                            const T* __restrict__ val,
                                                            const T* __restrict__ P, T c,
@@ -954,7 +954,7 @@ __global__ __launch_bounds__(kBlock) void poly_real_last_kernel(int n, const T* 
 
 // Pair, first half: Tt = A P ; Y (+)= c1 P - c2 Tt.
 template <class T, bool FIRST>
-__global__ __launch_bounds__(kBlock) void poly_pair1_kernel(int n, const int* __restrict__ rp,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void poly_pair1_kernel(int n, const int* __restrict__ rp,
                                                             const int* __restrict__ ci,
                                                             const T* __restrict__ val,
                                                             const T* __restrict__ P, T c1, T c2,
@@ -978,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void poly_pair1_kernel(int n, const int* __
 
 // Pair, second half: P_next = P - (c1 Tt - c2 A Tt).
 template <class T>
-__global__ __launch_bounds__(kBlock) void poly_pair2_kernel(int n, const int* __restrict__ rp,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void poly_pair2_kernel(int n, const int* __restrict__ rp,
                                                             const int* __restrict__ ci,
                                                             const T* __restrict__ val,
                                                             const T* __restrict__ P,
