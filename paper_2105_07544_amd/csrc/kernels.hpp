@@ -136,7 +136,7 @@ __device__ __forceinline__ void store_quad(T* dst, const T (&p)[4]) {
 }
 
 // Computes, for thread t of the block, the dot products of rows
-// r0 + t + i * kBlock (i < kSpmvRpt) with x (x scaled by `s` when SCALED) into
+// r0 + t + i * kBlock (i < RPT, by default kSpmvRpt) with x (x scaled by `s` when SCALED) into
 // acc[i]; 0 for rows past the last one.  The block's nonzeros are processed in
 // passes of SpmvCfg<T>::kChunk entries that start on a multiple of 4.  In a
 // pass each thread takes up to Q quads of (col, val) with vector loads (none
@@ -152,14 +152,14 @@ __device__ __forceinline__ void store_quad(T* dst, const T (&p)[4]) {
 // together with those uniform row bounds (one round trip for both instead of
 // one before the other); when it is set the whole block returns false and the
 // caller skips its epilogue.
-template <class T, bool SCALED, int CH = SpmvCfg<T>::kChunk>
+template <class T, bool SCALED, int CH = SpmvCfg<T>::kChunk, int RPT = kSpmvRpt>
 __device__ __forceinline__ bool spmv_rows(int n, int r0, const int* __restrict__ rp,
                                           const int* __restrict__ ci, const T* __restrict__ val,
-                                          const T* __restrict__ x, T s, T* s_prod, T (&acc)[kSpmvRpt],
+                                          const T* __restrict__ x, T s, T* s_prod, T (&acc)[RPT],
                                           const int* __restrict__ done = nullptr) {
   constexpr int Q = CH / (4 * kBlock);  // quads per thread per pass
   const int t = threadIdx.x;
-  const int nr = min(kSpmvRows, n - r0);
+  const int nr = min(kBlock * RPT, n - r0);
   // without a flag the load reads row_ptr[0] (0 by the CSR convention), so
   // the four uniform loads have no branch between them
   const int* flag = done ? done : rp;
@@ -167,9 +167,9 @@ __device__ __forceinline__ bool spmv_rows(int n, int r0, const int* __restrict__
   const int k1 = rp[r0 + nr];
   const int nnz = rp[n];
   if (*flag != 0 && done) return false;
-  int rs[kSpmvRpt], re[kSpmvRpt];
+  int rs[RPT], re[RPT];
 #pragma unroll
-  for (int i = 0; i < kSpmvRpt; ++i) {
+  for (int i = 0; i < RPT; ++i) {
     const int rl = t + i * kBlock;
     rs[i] = (rl < nr) ? rp[r0 + rl] : 0;
     re[i] = (rl < nr) ? rp[r0 + rl + 1] : 0;
@@ -212,7 +212,7 @@ __device__ __forceinline__ bool spmv_rows(int n, int r0, const int* __restrict__
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSpmvRpt; ++i) {
+    for (int i = 0; i < RPT; ++i) {
       const int lo = max(rs[i], base);
       const int hi = min(re[i], base + CH);
       for (int k = lo; k < hi; ++k) acc[i] += s_prod[k - base];
@@ -1131,8 +1131,9 @@ __global__ __launch_bounds__(kBlock) void small_cycle_kernel(
 // the multi-kernel cycle pays about eight launches per iteration.  Here a
 // cooperative launch of G co-resident blocks runs the whole restart cycle, with
 // grid barriers where the multi-kernel cycle has kernel boundaries that carry
-// data between blocks: four per inner iteration (five beyond 64 basis
-// columns, where the first update and the second dots run apart).
+// data between blocks: three per inner iteration of GMRES-IR, four for plain
+// GMRES (one more beyond 64 basis columns, where the first update and the
+// second dots run apart).
 // Above about 6000 rows the grid barriers cost more than the launches they
 // replace (n = 9216: 34.7 ms per GMRES-IR solve against 29.3 for the
 // multi-kernel cycle).
@@ -1191,25 +1192,30 @@ __device__ __forceinline__ void coop_take_cols(int j, int G, const double* __res
   }
 }
 
-// 1 / beta of the latest column from the norm partials, as the Givens step
+// beta of the latest column from the norm partials, as the Givens step
 // computes it (same partial sum, same roundings), so every block has it.
 template <class T>
-__device__ __forceinline__ double coop_inv_beta(int G, const double* __restrict__ part) {
-  __shared__ double s_ib;
+__device__ __forceinline__ double coop_beta(int G, const double* __restrict__ part) {
+  __shared__ double s_b;
   const double s = sum_partials(G, part);
-  if (threadIdx.x == 0) s_ib = 1.0 / double(T(sqrt(double(T(s)))));
+  if (threadIdx.x == 0) s_b = double(T(sqrt(double(T(s)))));
   __syncthreads();
-  return s_ib;
+  return s_b;
 }
 
 // One whole restart cycle on G = gridDim.x co-resident blocks (cooperative
 // launch): the cast of r, up to mc inner iterations, the solution update and
-// the next residual with its norm.  Per iteration: the SpMV of the rows of the
-// block's 512-row groups | barrier | CGS2 dots | barrier | update + dots |
-// barrier | update + norm | barrier; every block then takes 1 / beta from the
-// norm partials and goes on with the next SpMV while block 0 runs the float64
-// Givens step, whose flags the others read after the next barrier.  Sums of
-// block partials are added in block order (deterministic).
+// the next residual with its norm.  Per iteration: the SpMV | CGS2 dots |
+// barrier | update + dots | barrier | update + norm | barrier; every block
+// then takes beta from the norm partials and goes on with the next SpMV while
+// block 0 runs the float64 Givens step.  The SpMV walks 256-row groups, one
+// row per thread, so a block's SpMV rows are exactly the rows its waves take
+// in the dots and the fused update + dots, and no barrier separates them.
+// Only when the Givens step may end the cycle early (the implicit residual
+// test of plain GMRES) does a barrier follow the SpMV, after which every block
+// reads block 0's flags; without it (GMRES-IR) the only early end is a
+// breakdown, which every block sees in beta.  Sums of block partials are
+// added in block order (deterministic).
 template <class TI, class TO>
 __global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
     int n, const int* __restrict__ rp, const int* __restrict__ ci, const TI* __restrict__ vin,
@@ -1239,28 +1245,30 @@ __global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
     inv_beta = s_ib0;
   }
   if (blockIdx.x == 0) finish_start_cycle_body<TI>(G, partA, cs, stop_rel);
+  const bool implicit_stop = stop_rel >= 0.0;
   TI* wc = w0;  // the current w (the unnormalised v_j)
   TI* wn = w1;  // A v_j
   for (int j = 0; j < mc; ++j) {
     TI* vj = V + (size_t)j * ldv;
     const TI s = TI(inv_beta);
-    for (int r0 = blockIdx.x * kSpmvRows; r0 < n; r0 += G * kSpmvRows) {
-      TI acc[kSpmvRpt];
-      spmv_rows<TI, true, kChunk>(n, r0, rp, ci, vin, wc, s, s_pi, acc);
-#pragma unroll
-      for (int i = 0; i < kSpmvRpt; ++i) {
-        const int row = r0 + threadIdx.x + i * kBlock;
-        if (row < n) {
-          vj[row] = wc[row] * s;
-          wn[row] = acc[i];
-        }
+    for (int r0 = blockIdx.x * kBlock; r0 < n; r0 += G * kBlock) {
+      TI acc[1];
+      spmv_rows<TI, true, kChunk, 1>(n, r0, rp, ci, vin, wc, s, s_pi, acc);
+      const int row = r0 + threadIdx.x;
+      if (row < n) {
+        vj[row] = wc[row] * s;
+        wn[row] = acc[0];
       }
     }
-    grid_sync(bar, gen, st);
-    // block 0's Givens step of the previous column is complete: the cycle may be over
-    if (threadIdx.x == 0) s_done = st->done || st->barrier_timeout;
-    __syncthreads();
-    if (s_done) break;
+    if (implicit_stop) {
+      grid_sync(bar, gen, st);
+      // block 0's Givens step of the previous column is complete: the cycle may be over
+      if (threadIdx.x == 0) s_done = st->done || st->barrier_timeout;
+      __syncthreads();
+      if (s_done) break;
+    } else {
+      __syncthreads();  // the block's own rows of w and v_j, read next by its own waves
+    }
     const int jj = j + 1;  // basis columns
     if (jj <= 8) cgs_dots_body<TI, 8, 1>(n, jj, V, ldv, wn, partA, nullptr);
     else if (jj <= 16) cgs_dots_body<TI, 16, 1>(n, jj, V, ldv, wn, partA, nullptr);
@@ -1288,8 +1296,11 @@ __global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
     __syncthreads();
     cgs_update_norm_body<TI>(n, jj, V, ldv, s_h, wn, partA, nullptr);
     grid_sync(bar, gen, st);
-    inv_beta = coop_inv_beta<TI>(G, partA);
+    const double beta = coop_beta<TI>(G, partA);
+    inv_beta = 1.0 / beta;
     if (blockIdx.x == 0) finish_norm_body<TI, kTailGivens>(G, partA, cs, jj, mc - 1, thresh, nullptr, nullptr);
+    // a breakdown ends the cycle here in every block (the Givens step flags it too)
+    if (!implicit_stop && !(beta > thresh && isfinite(beta))) break;
     TI* t = wc;
     wc = wn;
     wn = t;

@@ -187,16 +187,18 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(int n, const int* __restr
         d = v;
       } else {
         r += fabs(v);
-        // a_ji by binary search in row j
+        // a_ji by binary search in row j; when row j stores no a_ji, the
+        // unstored entry (j, i) of A - A^T contributes a_ij^2 as well
         int lo = rp[j], hi = rp[j + 1] - 1;
         double vt = 0.0;
+        bool found = false;
         while (lo <= hi) {
           const int mid = (lo + hi) >> 1;
           const int cm = ci[mid];
-          if (cm == i) { vt = double(val[mid]); break; }
+          if (cm == i) { vt = double(val[mid]); found = true; break; }
           if (cm < i) lo = mid + 1; else hi = mid - 1;
         }
-        ns += (v - vt) * (v - vt);
+        ns += found ? (v - vt) * (v - vt) : 2.0 * v * v;
       }
     }
     if (r > 0.0) {

@@ -83,8 +83,13 @@ def test_matrix_stats_match_dense_definitions():
 
 def test_matrix_features_match_oracle():
     import oracle.features as F
+    # the last two: fewer rows than Arnoldi steps (n = 3, the hand-worked pin) and n = 1
+    D3 = np.array([[2.0, -1.0, 0.0], [0.0, 3.0, -1.0], [-1.0, 0.0, 4.0]])
+    hand = W.CSR(3, np.array([0, 2, 4, 6], dtype=np.int32), np.array([0, 1, 1, 2, 0, 2], dtype=np.int32),
+                 D3[D3 != 0].astype(np.float64))
+    one = W.CSR(1, np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32), np.array([3.0]))
     mats = [W.laplace2d(9), W.laplace3d(5), W.convdiff2d(11, 0.01, lambda x, y: (np.cos(3 * x), np.sin(2 * y))),
-            W.convdiff2d(40, 1e-3, lambda x, y: (np.cos(np.pi * x), np.sin(np.pi * y)))]
+            W.convdiff2d(40, 1e-3, lambda x, y: (np.cos(np.pi * x), np.sin(np.pi * y))), hand, one]
     for i, A in enumerate(mats):
         v0 = W.uniform_pm1(300 + i, A.n)
         say("features", i, A.n)
