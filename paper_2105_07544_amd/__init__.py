@@ -266,7 +266,7 @@ def gmres_solve(A: DeviceCSR, b: torch.Tensor, x: Optional[torch.Tensor] = None,
                 graph: bool = False, persistent: bool = False, stop_on_loss: bool = False,
                 half_basis: bool = False):
     """Restarted GMRES(m) in A's precision.  x (x0, updated in place) defaults to 0.
-    persistent: one single-block kernel per restart cycle for small systems.
+    persistent: one launch per restart cycle (one block up to n = 1024, a cooperative grid up to n = 6144).
     stop_on_loss: end at the first loss of accuracy instead of restarting.
     half_basis: passed through as GMR_FLAG_HALF_BASIS (only GMRES-IR supports it)."""
     if x is None:
@@ -291,7 +291,7 @@ def gmres_ir_solve(A64: DeviceCSR, A32: DeviceCSR, b: torch.Tensor, x: Optional[
                    ws: Optional[torch.Tensor] = None, prof="none", graph: bool = False,
                    persistent: bool = False, half_basis: bool = False):
     """GMRES-IR: float32 inner GMRES(m) on A32, float64 residual and update on A64.
-    persistent: one single-block kernel per restart cycle for small systems.
+    persistent: one launch per restart cycle (one block up to n = 1024, a cooperative grid up to n = 6144).
     half_basis: store the inner Krylov basis in float16 (no preconditioner)."""
     if x is None:
         x = torch.zeros_like(b)
