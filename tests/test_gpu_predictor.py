@@ -61,8 +61,16 @@ def test_adam_step_matches_oracle():
         assert np.allclose(net.theta.cpu().numpy(), th_o, rtol=1e-5, atol=1e-6)
 
 
+def _hand3():
+    # a_12, a_23 and a_31 have no stored transpose: ||A - A^T||_F^2 counts each twice
+    D3 = np.array([[2.0, -1.0, 0.0], [0.0, 3.0, -1.0], [-1.0, 0.0, 4.0]])
+    return W.CSR(3, np.array([0, 2, 4, 6], dtype=np.int32), np.array([0, 1, 1, 2, 0, 2], dtype=np.int32),
+                 D3[D3 != 0].astype(np.float64))
+
+
 def test_matrix_stats_match_dense_definitions():
-    mats = [W.laplace2d(9), W.laplace3d(5), W.convdiff2d(11, 0.01, lambda x, y: (np.cos(3 * x), np.sin(2 * y)))]
+    mats = [W.laplace2d(9), W.laplace3d(5), W.convdiff2d(11, 0.01, lambda x, y: (np.cos(3 * x), np.sin(2 * y))),
+            _hand3()]
     for A in mats:
         D = A.to_dense()
         s = PR.matrix_stats(G.DeviceCSR.from_host(A, DEV))
@@ -84,9 +92,7 @@ def test_matrix_stats_match_dense_definitions():
 def test_matrix_features_match_oracle():
     import oracle.features as F
     # the last two: fewer rows than Arnoldi steps (n = 3, the hand-worked pin) and n = 1
-    D3 = np.array([[2.0, -1.0, 0.0], [0.0, 3.0, -1.0], [-1.0, 0.0, 4.0]])
-    hand = W.CSR(3, np.array([0, 2, 4, 6], dtype=np.int32), np.array([0, 1, 1, 2, 0, 2], dtype=np.int32),
-                 D3[D3 != 0].astype(np.float64))
+    hand = _hand3()
     one = W.CSR(1, np.array([0, 1], dtype=np.int32), np.array([0], dtype=np.int32), np.array([3.0]))
     mats = [W.laplace2d(9), W.laplace3d(5), W.convdiff2d(11, 0.01, lambda x, y: (np.cos(3 * x), np.sin(2 * y))),
             W.convdiff2d(40, 1e-3, lambda x, y: (np.cos(np.pi * x), np.sin(np.pi * y))), hand, one]
