@@ -963,8 +963,8 @@ def main():
         summarize_pmc(*args.summarize_pmc, args.workload, dom, pats, args.copy_calibration or 1024)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
-              "multi-GPU path; the sharded design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the solver has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import paper_2105_07544_amd as G
     G.lib()  # fails loudly when the HIP library is not built

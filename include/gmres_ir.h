@@ -52,7 +52,7 @@ typedef enum {
   GMR_ERR_HIP = -2,          /* a HIP call failed                                        */
   GMR_ERR_WORKSPACE = -3,    /* workspace smaller than gmres_workspace_bytes()           */
   GMR_ERR_NONFINITE = -4,    /* NaN/Inf in b, in a residual norm or in the Hessenberg    */
-  GMR_ERR_UNSUPPORTED = -5   /* parameter outside what this build supports               */
+  GMR_ERR_UNSUPPORTED = -5   /* parameter outside what this library supports             */
 } gmr_status;
 
 /* CSR matrix; all three arrays are device pointers. */

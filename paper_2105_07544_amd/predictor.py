@@ -34,7 +34,7 @@ RESTARTS = (25, 50, 100, 200)
 DEGREES = (0, 5, 10, 25, 40)
 PRECISIONS = ("f32", "f64")
 COMBOS = [(m, d, p) for m in RESTARTS for d in DEGREES for p in PRECISIONS]
-BASELINE = (50, 0, "f32")
+FIXED_COMBO = (50, 0, "f32")
 NFEAT = 16
 # layer shapes of the network, in the order of the flat parameter vector
 LAYERS = [(64, NFEAT), (64,), (64, 64), (64,), (11, 64), (11,)]
@@ -168,7 +168,7 @@ def evaluate(net: Net, ds: Dataset):
     combination when the predicted one fails, both charged) against the fixed
     combination alone, over the systems the fixed combination solves."""
     pred = net.predict(ds.X)
-    kb = combo_index(BASELINE)
+    kb = combo_index(FIXED_COMBO)
     tb = ds.times[:, kb]
     tp = np.empty(len(pred))
     fallbacks = 0
@@ -236,13 +236,13 @@ def label_system(sysd, v0: np.ndarray, device="cuda", base_cap_s: float = 4.0, m
     A64, A32, b = device_system(sysd, device)
     v = torch.from_numpy(v0).to(device)
     feats = features(A64, v.double())
-    _chunked_solve(A64, A32, b, BASELINE, v, 0.0, 50)  # warm-up of the kernels at this size
+    _chunked_solve(A64, A32, b, FIXED_COMBO, v, 0.0, 50)  # warm-up of the kernels at this size
     times = np.full(len(COMBOS), math.inf)
     bounds = np.zeros(len(COMBOS))
     iters = np.zeros(len(COMBOS), dtype=np.int64)
     capped = np.zeros(len(COMBOS), dtype=bool)
-    kb = combo_index(BASELINE)
-    t, ok, it, cp = _chunked_solve(A64, A32, b, BASELINE, v, base_cap_s, max_iters)
+    kb = combo_index(FIXED_COMBO)
+    t, ok, it, cp = _chunked_solve(A64, A32, b, FIXED_COMBO, v, base_cap_s, max_iters)
     bounds[kb], iters[kb], capped[kb] = t, it, cp
     if ok:
         times[kb] = t
@@ -286,9 +286,9 @@ def evaluate_system(net: "Net", sysd, v0: np.ndarray, device="cuda", base_cap_s:
     v = torch.from_numpy(v0).to(device)
     f = features(A64, v.double())
     pred = net.predict(f[None, :])[0]
-    _chunked_solve(A64, A32, b, BASELINE, v, 0.0, 50)  # warm-up of the kernels at this size
-    tb, okb, itb, _ = _chunked_solve(A64, A32, b, BASELINE, v, base_cap_s, max_iters)
-    if pred == BASELINE:
+    _chunked_solve(A64, A32, b, FIXED_COMBO, v, 0.0, 50)  # warm-up of the kernels at this size
+    tb, okb, itb, _ = _chunked_solve(A64, A32, b, FIXED_COMBO, v, base_cap_s, max_iters)
+    if pred == FIXED_COMBO:
         tp, okp, itp, fb = tb, okb, itb, False
     else:
         tp, okp, itp, _ = _chunked_solve(A64, A32, b, pred, v, base_cap_s, max_iters)
