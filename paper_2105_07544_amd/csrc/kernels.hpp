@@ -1145,34 +1145,37 @@ constexpr int kCoopMaxBlocks = 64;
 constexpr int kCoopAlt = kPartPitch / 2;
 static_assert(kCoopMaxBlocks <= kCoopAlt, "partials of one pass must fit half a column pitch");
 
-// Grid-wide barrier on device-scope vector atomics: thread 0 of each block
-// publishes the block's writes (release), counts itself in, and the last one
-// resets the count and advances the generation that the others wait on
-// (acquire).  All blocks of a cooperative launch are resident, so every wait
-// ends; a wait that has not ended after about a second gives up, flags
-// barrier_timeout and lets the kernel run to its end, so a broken barrier
-// cannot hang the device.
+// Grid-wide barrier on device-scope vector atomics.  After the block barrier,
+// thread 0 of each block counts itself in with a release add, which makes the
+// block's writes visible at device scope.  The last to arrive takes an acquire
+// fence, resets the count and publishes the next generation with a release
+// store; the others poll the generation with relaxed loads and take a single
+// acquire fence once it has moved (an acquire on every poll would invalidate
+// the caches on every probe).  All blocks of a cooperative launch are
+// resident, so every wait ends; a wait that has not ended after about a second
+// gives up, flags barrier_timeout and lets the kernel run to its end, so a
+// broken barrier cannot hang the device.
 __device__ __forceinline__ void grid_sync(GridBarrier* bar, unsigned int& gen, Status* st) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     const unsigned int g = gen;
     const unsigned int arrived =
-        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == gridDim.x - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&bar->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       int spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         __builtin_amdgcn_s_sleep(2);
         if (++spins > (1 << 24)) {
           __hip_atomic_store(&st->barrier_timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __threadfence();
   }
   gen += 1;
   __syncthreads();
