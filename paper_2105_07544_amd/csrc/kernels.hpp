@@ -1155,28 +1155,50 @@ static_assert(kCoopMaxBlocks <= kCoopAlt, "partials of one pass must fit half a 
 // resident, so every wait ends; a wait that has not ended after about a second
 // gives up, flags barrier_timeout and lets the kernel run to its end, so a
 // broken barrier cannot hang the device.
-__device__ __forceinline__ void grid_sync(GridBarrier* bar, unsigned int& gen, Status* st) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int g = gen;
-    const unsigned int arrived =
-        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == gridDim.x - 1) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      int spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1 << 24)) {
-          __hip_atomic_store(&st->barrier_timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// Thread 0: count the block in; the last to arrive publishes generation g+1.
+// Returns whether this block was the last.
+__device__ __forceinline__ bool grid_arrive(GridBarrier* bar, unsigned int g) {
+  const unsigned int arrived =
+      __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (arrived != gridDim.x - 1) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&bar->gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+// Thread 0: wait until generation g has passed (bounded).
+__device__ __forceinline__ void grid_wait(GridBarrier* bar, unsigned int g, Status* st) {
+  int spins = 0;
+  while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > (1 << 24)) {
+      __hip_atomic_store(&st->barrier_timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void grid_sync(GridBarrier* bar, unsigned int& gen, Status* st) {
+  __syncthreads();
+  if (threadIdx.x == 0 && !grid_arrive(bar, gen)) grid_wait(bar, gen, st);
+  gen += 1;
+  __syncthreads();
+}
+
+// grid_sync in which block 0 runs work0 (with all its threads) after it has
+// arrived and before it waits, so that work no other block needs before a
+// later barrier overlaps the wait instead of delaying block 0's arrival.
+// work0's writes are published by the next barrier.
+template <class F>
+__device__ __forceinline__ void grid_sync_then(GridBarrier* bar, unsigned int& gen, Status* st, F&& work0) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = grid_arrive(bar, gen) ? 1 : 0;
+  __syncthreads();
+  if (blockIdx.x == 0) work0();
+  if (threadIdx.x == 0 && !s_last) grid_wait(bar, gen, st);
   gen += 1;
   __syncthreads();
 }
@@ -1210,8 +1232,9 @@ __device__ __forceinline__ double coop_beta(int G, const double* __restrict__ pa
 // launch): the cast of r, up to mc inner iterations, the solution update and
 // the next residual with its norm.  Per iteration: the SpMV | CGS2 dots |
 // barrier | update + dots | barrier | update + norm | barrier; every block
-// then takes beta from the norm partials and goes on with the next SpMV while
-// block 0 runs the float64 Givens step.  The SpMV walks 256-row groups, one
+// then takes beta from the norm partials and goes on with the next SpMV;
+// block 0 runs the float64 Givens step first (plain GMRES) or inside the next
+// iteration's first barrier (GMRES-IR).  The SpMV walks 256-row groups, one
 // row per thread, so a block's SpMV rows are exactly the rows its waves take
 // in the dots and the fused update + dots, and no barrier separates them.
 // Only when the Givens step may end the cycle early (the implicit residual
@@ -1251,6 +1274,11 @@ __global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
   const bool implicit_stop = stop_rel >= 0.0;
   TI* wc = w0;  // the current w (the unnormalised v_j)
   TI* wn = w1;  // A v_j
+  // Without the implicit residual test no block reads the Givens step before
+  // the cycle ends: block 0 then runs column j's step while it waits at the
+  // next iteration's first barrier (same steps, same order, same results).
+  int pend_jc = -1;
+  double pend_beta = 0.0;
   for (int j = 0; j < mc; ++j) {
     TI* vj = V + (size_t)j * ldv;
     const TI s = TI(inv_beta);
@@ -1279,7 +1307,12 @@ __global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
     else if (jj <= 64) cgs_dots_body<TI, 64, 1>(n, jj, V, ldv, wn, partA, nullptr);
     else if (jj <= 256) cgs_dots_body<TI, 64, 4>(n, jj, V, ldv, wn, partA, nullptr);
     else cgs_dots_body<TI, 64, 8>(n, jj, V, ldv, wn, partA, nullptr);
-    grid_sync(bar, gen, st);
+    if (pend_jc >= 0) {
+      grid_sync_then(bar, gen, st, [&] { givens_tail(cs, pend_jc, mc - 1, pend_beta, thresh); });
+      pend_jc = -1;
+    } else {
+      grid_sync(bar, gen, st);
+    }
     coop_take_cols<TI>(jj, G, partA, cs.h1d, s_h);
     __syncthreads();
     if (jj <= 8) cgs_update_dots_body<TI, 8>(n, jj, V, ldv, s_h, wn, partB, nullptr);
@@ -1301,7 +1334,12 @@ __global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
     grid_sync(bar, gen, st);
     const double beta = coop_beta<TI>(G, partA);
     inv_beta = 1.0 / beta;
-    if (blockIdx.x == 0) finish_norm_body<TI, kTailGivens>(G, partA, cs, jj, mc - 1, thresh, nullptr, nullptr);
+    if (implicit_stop) {
+      if (blockIdx.x == 0) finish_norm_body<TI, kTailGivens>(G, partA, cs, jj, mc - 1, thresh, nullptr, nullptr);
+    } else {
+      pend_jc = jj - 1;
+      pend_beta = beta;
+    }
     // a breakdown ends the cycle here in every block (the Givens step flags it too)
     if (!implicit_stop && !(beta > thresh && isfinite(beta))) break;
     TI* t = wc;
@@ -1309,6 +1347,7 @@ __global__ __launch_bounds__(kBlock) void coop_cycle_kernel(
     wn = t;
   }
   // y and k of block 0's last Givens step
+  if (pend_jc >= 0 && blockIdx.x == 0) givens_tail(cs, pend_jc, mc - 1, pend_beta, thresh);
   grid_sync(bar, gen, st);
   solution_update_body<TI, TO>(n, V, ldv, cs.y, st, nullptr, x);
   grid_sync(bar, gen, st);
