@@ -538,3 +538,31 @@ def test_cooperative_cycle_matches_multikernel(n_side, restart):
         # deterministic: block partials are added in block order
         xc, rc = f(restart=restart, tol=1e-10, max_iters=40000, persistent=True)
         assert np.array_equal(host(xb), host(xc)) and rb.history == rc.history
+
+
+def test_cooperative_cycle_lucky_breakdown():
+    # b = 3 e_8 on a diagonal matrix: v_1 = e_8 exactly, A v_1 = a_88 v_1, and
+    # both CGS passes leave w = 0 exactly in either precision, so every cycle
+    # ends by breakdown after one column (in GMRES-IR the cooperative cycle
+    # takes that column's Givens step after leaving the loop).  a_88 = 5, so
+    # the float32 correction 1/5 is inexact and IR needs more than one cycle.
+    n = 2000
+    d = 2.0 + (np.arange(n) % 5).astype(np.float64)
+    A_h = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b_h = np.zeros(n)
+    b_h[8] = 3.0
+    A = dev(A_h)
+    A32 = A.to_f32()
+    for name, f in (("f64", lambda **k: G.gmres_solve(A, t64(b_h), **k)),
+                    ("ir", lambda **k: G.gmres_ir_solve(A, A32, t64(b_h), **k))):
+        say("lucky breakdown", name)
+        xa, ra = f(restart=50, tol=1e-10, max_iters=1000)
+        xb, rb = f(restart=50, tol=1e-10, max_iters=1000, persistent=True)
+        say(ra.iters, ra.cycles, rb.iters, rb.cycles, rb.rel_res)
+        for r in (ra, rb):
+            assert r.converged and r.iters == r.cycles
+        assert (ra.iters, ra.cycles) == (rb.iters, rb.cycles)
+        # one nonzero product per sum: the block order cannot change a bit
+        assert np.array_equal(host(xa), host(xb))
+        assert np.linalg.norm(b_h - O.spmv(A_h, host(xb))) / np.linalg.norm(b_h) <= 1e-10
+        assert np.count_nonzero(host(xb)) == 1
