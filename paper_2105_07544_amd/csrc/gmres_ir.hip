@@ -534,7 +534,14 @@ static gmr_status poly_apply_impl(Ctx& c, const gmr_poly* P, const gmr_csr* A, c
   T* bufs[2] = {P0, P1};
   int nb = 0;
   bool first = true;
-  const double step_bytes = spmv_bytes<T>(A) + 3.0 * n * sizeof(T);
+  // Algorithmic bytes of a step: the matrix and the gathered input (whose own
+  // rows, read again by the epilogue, count once), plus the epilogue's other
+  // vectors.  A real step and pair step 1 write y and the next vector (the next
+  // P, or Tt) and read y after the first step; pair step 2 reads P and writes
+  // the next P (Tt is its gathered input).
+  const double vec = (double)n * sizeof(T);
+  const double mat_x = spmv_bytes<T>(A) - vec;
+  auto step_bytes = [&](bool f) { return mat_x + (f ? 2.0 : 3.0) * vec; };
   int i = 0;
   while (i < k) {
     if (P->im[i] == 0.0) {
@@ -548,7 +555,7 @@ static gmr_status poly_apply_impl(Ctx& c, const gmr_poly* P, const gmr_csr* A, c
         else
           poly_real_kernel<T, false><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, cr, y, nxt, done);
         GMR_TRY(check_launch("poly_real_kernel"));
-        GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes));
+        GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes(first)));
         cur = nxt;
       } else {
         if (first)
@@ -568,14 +575,14 @@ static gmr_status poly_apply_impl(Ctx& c, const gmr_poly* P, const gmr_csr* A, c
       else
         poly_pair1_kernel<T, false><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, c1, c2, y, Tt, done);
       GMR_TRY(check_launch("poly_pair1_kernel"));
-      GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes + (double)n * sizeof(T)));
+      GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes(first)));
       if (i < k - 2) {
         T* nxt = bufs[nb];
         nb ^= 1;
         GMR_TRY(c.begin(GMR_PROF_POLY_STEP));
         poly_pair2_kernel<T><<<G, kBlock, 0, c.s>>>(n, rp, ci, val, cur, Tt, c1, c2, nxt, done);
         GMR_TRY(check_launch("poly_pair2_kernel"));
-        GMR_TRY(c.end(GMR_PROF_POLY_STEP, step_bytes));
+        GMR_TRY(c.end(GMR_PROF_POLY_STEP, mat_x + 2.0 * vec));
         cur = nxt;
       }
       i += 2;
@@ -772,7 +779,8 @@ static gmr_status solve_impl(const SolveArgs& a) {
                                                          (const TO*)a.Aout->val, x, b, r,
                                                          ws.partial());
     GMR_TRY(check_launch("residual_kernel"));
-    GMR_TRY(c.end(GMR_PROF_RESIDUAL, spmv_bytes<TO>(a.Aout) + 2.0 * n * sizeof(TO)));
+    // the product (matrix, gathered x, r written) and b read
+    GMR_TRY(c.end(GMR_PROF_RESIDUAL, spmv_bytes<TO>(a.Aout) + (double)n * sizeof(TO)));
     finish_residual_kernel<<<1, kBlock, 0, c.s>>>(spmv_grid(n), ws.partial(), st_dev);
     return check_launch("finish_residual_kernel");
   };
